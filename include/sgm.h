@@ -1,0 +1,141 @@
+/*
+ * sgm.h -- C ABI of libsgm.so, the MI355X (gfx950) SGM stereo hot path.
+ *
+ * The calls follow the problem statement of Ruf et al., 2021, "ReS2tAC --
+ * UAV-borne real-time SGM stereo optimized for embedded ARM and CUDA devices":
+ * a rectified grey-value pair, a disparity range Gamma = {0 .. ndisp-1}, the
+ * census/Hamming matching cost (Sec. 2.1.1, Eq. image_matching), the SGM path
+ * aggregation (Sec. 2.1.2, Eq. sgm_path and Eq. sgm_path_aggr), and the
+ * disparity selection with its post-processing (Eq. wta, Eq. right_disparity,
+ * Eq. LR_check, the 3x3 median of Sec. 2.1.3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every buffer pointer is a DEVICE pointer, allocated and owned by the
+ *    caller.  Inputs are never written.  Outputs must not alias inputs.
+ *  - Layout is row-major.  Maps are [height][width]; volumes are
+ *    [height][width][ndisp] with the disparity index fastest (contiguous).
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
+ *    is the default stream).  No call allocates device memory or synchronises.
+ *  - Every argument is validated before anything is enqueued.  On any error
+ *    nothing is launched and nothing is written; the status tells why.
+ *    Faults inside a launched kernel surface at the caller's next
+ *    synchronisation of `stream`.
+ *  - All arithmetic is integer; results are bit-exact and do not depend on
+ *    launch shape, stream or timing.
+ *  - Calls are reentrant; calls on different streams may run concurrently
+ *    when their buffers are distinct.
+ *  - Disparity maps are uint16 with SGM_INVALID (0xFFFF) marking invalid
+ *    pixels.
+ */
+#ifndef SGM_H
+#define SGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGM_INVALID 0xFFFFu
+#define SGM_MAX_NDISP 256
+
+typedef enum {
+    SGM_OK = 0,
+    SGM_ERR_ARG = -1,          /* null pointer, size or parameter out of range      */
+    SGM_ERR_UNSUPPORTED = -2,  /* census window other than 5x5 or 9x7               */
+    SGM_ERR_ALIGN = -3,        /* pointer not aligned as documented below           */
+    SGM_ERR_HIP = -4,          /* a HIP launch failed; see sgm_last_hip_error()     */
+    SGM_ERR_WORKSPACE = -5     /* workspace missing or too small                    */
+} sgm_status;
+
+/*
+ * Census transform (Sec. 2.2.1; centre omitted as in Sec. 2.3.1).
+ * For every pixel p one bit [I(q) < I(p)] per neighbour q of a win_w x win_h
+ * window (centre excluded), in raster order (rows top to bottom, columns left
+ * to right), the first neighbour in the highest used bit; neighbours outside
+ * the image read as 0 (the zero-valued margin).
+ *   img         uint8 [height][pitch_bytes], 1-byte aligned, pitch_bytes >= width
+ *   win_w,win_h (5,5) -> 24 bits, or (9,7) = 9 columns x 7 rows -> 62 bits
+ *   census_out  uint64 [height][width], 8-byte aligned
+ * Errors: SGM_ERR_ARG (null, width/height < 1, pitch < width),
+ *         SGM_ERR_UNSUPPORTED (other windows), SGM_ERR_ALIGN.
+ */
+int32_t sgm_census(const uint8_t* img, int32_t width, int32_t height,
+                   int32_t pitch_bytes, int32_t win_w, int32_t win_h,
+                   uint64_t* census_out, void* stream);
+
+/*
+ * Matching-cost volume, Eq. (image_matching) with Phi the Hamming distance of
+ * census descriptors (Sec. 2.1.1):
+ *   C(x, y, d) = popcount(CL(x, y) ^ CR(x - d, y))   if x - d >= 0
+ *              = 255 (0xFF, no match; Sec. 2.3.1)    otherwise
+ *   census_left, census_right  uint64 [height][width], 8-byte aligned
+ *   ndisp                      1 .. 256
+ *   cost_out                   uint8 [height][width][ndisp], 16-byte aligned
+ * Errors: SGM_ERR_ARG, SGM_ERR_ALIGN.
+ */
+int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right,
+                 int32_t width, int32_t height, int32_t ndisp,
+                 uint8_t* cost_out, void* stream);
+
+/*
+ * SGM aggregation, Eq. (sgm_path) and Eq. (sgm_path_aggr) (Sec. 2.1.2):
+ *   L_r(p, d) = C(p, d) + min(L'(d), L'(d-1) + P1, L'(d+1) + P1, m' + P2) - m'
+ *   with L' = L_r(p - r, .) and m' = min_d L'(d); L_r = C at the first pixel
+ *   of a path; terms with d +- 1 outside Gamma drop out;
+ *   S_bar(p, d) = sum over the path set of L_r(p, d).
+ * Path sets: npaths = 4 -> the two horizontal and the two vertical paths
+ * (Sec. 3.1.4); npaths = 8 adds the four diagonals.
+ *   cost     uint8 [height][width][ndisp], 16-byte aligned
+ *   p1, p2   penalties with 0 <= p1 <= p2 and npaths * (255 + p2) <= 65535,
+ *            so that every S_bar fits uint16 exactly
+ *   agg_out  uint16 [height][width][ndisp], 16-byte aligned
+ * Errors: SGM_ERR_ARG (sizes, npaths not 4/8, p1 > p2, overflow bound),
+ *         SGM_ERR_ALIGN.
+ */
+int32_t sgm_aggregate(const uint8_t* cost, int32_t width, int32_t height,
+                      int32_t ndisp, int32_t npaths, int32_t p1, int32_t p2,
+                      uint16_t* agg_out, void* stream);
+
+/*
+ * Disparity selection and post-processing (Eq. wta, Eq. right_disparity,
+ * Eq. LR_check, Sec. 2.1.3):
+ *   D^L(p) = smallest d minimising S_bar(p, d)
+ *   D^R(p) = smallest d minimising S_bar((px + d, py), d) over px + d < width
+ *   LR check (lr_tolerance = t >= 0): D(p) = D^L(p) if px - D^L(p) >= 0 and
+ *            |D^L(p) - D^R(px - D^L(p), py)| <= t, else SGM_INVALID;
+ *            lr_tolerance < 0 skips the check (D = D^L).
+ *   median3x3 = 1: every valid pixel takes the median of its 3x3 window, in
+ *            which pixels outside the image and invalid pixels count as
+ *            0xFFFF; invalid pixels stay invalid.  0 skips the median.
+ *   agg             uint16 [height][width][ndisp], 16-byte aligned
+ *   disp_out        uint16 [height][width], 4-byte aligned
+ *   disp_right_out  uint16 [height][width] receiving D^R, or NULL
+ *   work            uint16 scratch of sgm_wta_lrc_work_elems(width, height)
+ *                   elements, 4-byte aligned; contents on return are
+ *                   unspecified
+ * Errors: SGM_ERR_ARG, SGM_ERR_ALIGN, SGM_ERR_WORKSPACE (work NULL).
+ */
+int32_t sgm_wta_lrc(const uint16_t* agg, int32_t width, int32_t height,
+                    int32_t ndisp, int32_t lr_tolerance, int32_t median3x3,
+                    uint16_t* disp_out, uint16_t* disp_right_out,
+                    uint16_t* work, void* stream);
+
+/* Number of uint16 elements sgm_wta_lrc needs in `work` (0 on bad sizes). */
+size_t sgm_wta_lrc_work_elems(int32_t width, int32_t height);
+
+/* Human-readable name of a status code. */
+const char* sgm_status_string(int32_t status);
+
+/* hipError_t of the most recent SGM_ERR_HIP on the calling thread. */
+int32_t sgm_last_hip_error(void);
+
+/* ABI version, incremented on every incompatible change. */
+int32_t sgm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGM_H */

@@ -1,0 +1,100 @@
+// sgm_capi.cpp -- the extern "C" entry points of include/sgm.h: argument
+// validation, then the kernel launches.  Nothing here allocates memory or
+// synchronises; every check happens before the first launch.
+#include "sgm.h"
+
+#include <hip/hip_runtime.h>
+
+#include "sgm_internal.h"
+
+namespace {
+
+thread_local int32_t g_last_hip_error = 0;
+
+constexpr int32_t kMaxSide = 32768;   // keeps every grid dimension in range
+
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+bool bad_size(int32_t width, int32_t height) {
+    return width < 1 || height < 1 || width > kMaxSide || height > kMaxSide;
+}
+
+int32_t hip_status(hipError_t e) {
+    if (e == hipSuccess) return SGM_OK;
+    g_last_hip_error = (int32_t)e;
+    return SGM_ERR_HIP;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+int32_t sgm_abi_version(void) { return 1; }
+
+const char* sgm_status_string(int32_t status) {
+    switch (status) {
+        case SGM_OK: return "SGM_OK";
+        case SGM_ERR_ARG: return "SGM_ERR_ARG: invalid argument";
+        case SGM_ERR_UNSUPPORTED: return "SGM_ERR_UNSUPPORTED: census window must be 5x5 or 9x7";
+        case SGM_ERR_ALIGN: return "SGM_ERR_ALIGN: misaligned buffer";
+        case SGM_ERR_HIP: return "SGM_ERR_HIP: HIP launch failed";
+        case SGM_ERR_WORKSPACE: return "SGM_ERR_WORKSPACE: workspace missing or too small";
+        default: return "unknown sgm status";
+    }
+}
+
+int32_t sgm_last_hip_error(void) { return g_last_hip_error; }
+
+int32_t sgm_census(const uint8_t* img, int32_t width, int32_t height, int32_t pitch_bytes,
+                   int32_t win_w, int32_t win_h, uint64_t* census_out, void* stream) {
+    if (!img || !census_out || bad_size(width, height) || pitch_bytes < width) return SGM_ERR_ARG;
+    if (!((win_w == 5 && win_h == 5) || (win_w == 9 && win_h == 7))) return SGM_ERR_UNSUPPORTED;
+    if (!aligned(census_out, 8)) return SGM_ERR_ALIGN;
+    return hip_status(sgm::launch_census(img, width, height, pitch_bytes, win_w, win_h,
+                                         census_out, as_stream(stream)));
+}
+
+int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right, int32_t width,
+                 int32_t height, int32_t ndisp, uint8_t* cost_out, void* stream) {
+    if (!census_left || !census_right || !cost_out || bad_size(width, height)) return SGM_ERR_ARG;
+    if (ndisp < 1 || ndisp > SGM_MAX_NDISP) return SGM_ERR_ARG;
+    if (!aligned(census_left, 8) || !aligned(census_right, 8) || !aligned(cost_out, 16))
+        return SGM_ERR_ALIGN;
+    return hip_status(sgm::launch_cost(census_left, census_right, width, height, ndisp, cost_out,
+                                       as_stream(stream)));
+}
+
+int32_t sgm_aggregate(const uint8_t* cost, int32_t width, int32_t height, int32_t ndisp,
+                      int32_t npaths, int32_t p1, int32_t p2, uint16_t* agg_out, void* stream) {
+    if (!cost || !agg_out || bad_size(width, height)) return SGM_ERR_ARG;
+    if (ndisp < 1 || ndisp > SGM_MAX_NDISP) return SGM_ERR_ARG;
+    if (npaths != 4 && npaths != 8) return SGM_ERR_ARG;
+    if (p1 < 0 || p2 < p1) return SGM_ERR_ARG;
+    if ((int64_t)npaths * (255 + (int64_t)p2) > 65535) return SGM_ERR_ARG;
+    if (!aligned(cost, 16) || !aligned(agg_out, 16)) return SGM_ERR_ALIGN;
+    return hip_status(sgm::launch_aggregate(cost, width, height, ndisp, npaths, p1, p2, agg_out,
+                                            as_stream(stream)));
+}
+
+size_t sgm_wta_lrc_work_elems(int32_t width, int32_t height) {
+    if (bad_size(width, height)) return 0;
+    return (size_t)3 * (size_t)width * (size_t)height;
+}
+
+int32_t sgm_wta_lrc(const uint16_t* agg, int32_t width, int32_t height, int32_t ndisp,
+                    int32_t lr_tolerance, int32_t median3x3, uint16_t* disp_out,
+                    uint16_t* disp_right_out, uint16_t* work, void* stream) {
+    if (!agg || !disp_out || bad_size(width, height)) return SGM_ERR_ARG;
+    if (ndisp < 1 || ndisp > SGM_MAX_NDISP) return SGM_ERR_ARG;
+    if (median3x3 != 0 && median3x3 != 1) return SGM_ERR_ARG;
+    if (!work) return SGM_ERR_WORKSPACE;
+    if (!aligned(agg, 16) || !aligned(disp_out, 4) || !aligned(work, 4) ||
+        (disp_right_out && !aligned(disp_right_out, 4)))
+        return SGM_ERR_ALIGN;
+    return hip_status(sgm::launch_wta_lrc(agg, width, height, ndisp, lr_tolerance, median3x3,
+                                          disp_out, disp_right_out, work, as_stream(stream)));
+}
+
+}  // extern "C"

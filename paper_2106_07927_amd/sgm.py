@@ -1,0 +1,219 @@
+"""Python binding of libsgm.so (include/sgm.h): argument marshalling only.
+
+Every function takes and returns torch CUDA tensors (device memory on the
+current ROCm device) and enqueues on the current torch stream unless a stream
+is given.  All computation happens in the HIP kernels of libsgm.so; there is
+no fallback: if the library is not built, or a tensor is not on the GPU, the
+call raises.
+
+Names follow the C ABI: sgm_census, sgm_cost, sgm_aggregate, sgm_wta_lrc.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsgm.so")
+INVALID = 0xFFFF
+
+SGM_OK = 0
+SGM_ERR_ARG = -1
+SGM_ERR_UNSUPPORTED = -2
+SGM_ERR_ALIGN = -3
+SGM_ERR_HIP = -4
+SGM_ERR_WORKSPACE = -5
+
+EXPORTS = ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_wta_lrc", "sgm_wta_lrc_work_elems",
+           "sgm_status_string", "sgm_last_hip_error", "sgm_abi_version")
+
+
+class SGMError(RuntimeError):
+    """A libsgm call returned a non-zero status."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsgm.so and declare its signatures (no GPU call is made)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2106_07927_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32 = ctypes.c_void_p, ctypes.c_int32
+    lib.sgm_census.argtypes = [P, I32, I32, I32, I32, I32, P, P]
+    lib.sgm_cost.argtypes = [P, P, I32, I32, I32, P, P]
+    lib.sgm_aggregate.argtypes = [P, I32, I32, I32, I32, I32, I32, P, P]
+    lib.sgm_wta_lrc.argtypes = [P, I32, I32, I32, I32, I32, P, P, P, P]
+    lib.sgm_wta_lrc_work_elems.argtypes = [I32, I32]
+    lib.sgm_wta_lrc_work_elems.restype = ctypes.c_size_t
+    lib.sgm_status_string.argtypes = [I32]
+    lib.sgm_status_string.restype = ctypes.c_char_p
+    lib.sgm_last_hip_error.argtypes = []
+    lib.sgm_abi_version.argtypes = []
+    for name in ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_wta_lrc",
+                 "sgm_last_hip_error", "sgm_abi_version"):
+        getattr(lib, name).restype = I32
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != SGM_OK:
+        lib = load_library()
+        msg = lib.sgm_status_string(status).decode()
+        if status == SGM_ERR_HIP:
+            msg += f" (hipError {lib.sgm_last_hip_error()})"
+        raise SGMError(status, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError("libsgm takes device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("libsgm takes contiguous tensors only")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _expect(t: torch.Tensor, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected {dtype} {tuple(shape)}, got {t.dtype} {tuple(t.shape)}")
+
+
+def _empty(shape, dtype, device, pad_bytes=16):
+    """Contiguous device tensor whose allocation extends to a 16-byte multiple."""
+    n = 1
+    for s in shape:
+        n *= s
+    item = torch.empty((), dtype=dtype).element_size()
+    total = (n * item + pad_bytes - 1) // pad_bytes * pad_bytes // item
+    return torch.empty(max(total, 1), dtype=dtype, device=device)[:n].view(shape)
+
+
+def sgm_census(img: torch.Tensor, win_w: int, win_h: int, out: Optional[torch.Tensor] = None,
+               width: Optional[int] = None, stream=None) -> torch.Tensor:
+    """Census transform.  img: uint8 [H][pitch] (width <= pitch, default all
+    columns); returns uint64 [H][W] descriptors."""
+    if img.dtype != torch.uint8 or img.dim() != 2:
+        raise ValueError("img must be a 2-D uint8 tensor")
+    h, pitch = img.shape
+    w = pitch if width is None else width
+    if out is None:
+        out = _empty((h, w), torch.uint64, img.device)
+    _expect(out, torch.uint64, (h, w), "out")
+    _check(load_library().sgm_census(_ptr(img), w, h, pitch, win_w, win_h, _ptr(out), _stream(stream)))
+    return out
+
+
+def sgm_cost(census_left: torch.Tensor, census_right: torch.Tensor, ndisp: int,
+             out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Hamming cost volume; returns uint8 [H][W][ndisp]."""
+    h, w = census_left.shape
+    _expect(census_left, torch.uint64, (h, w), "census_left")
+    _expect(census_right, torch.uint64, (h, w), "census_right")
+    if out is None:
+        out = _empty((h, w, ndisp), torch.uint8, census_left.device)
+    _expect(out, torch.uint8, (h, w, ndisp), "out")
+    _check(load_library().sgm_cost(_ptr(census_left), _ptr(census_right), w, h, ndisp,
+                                   _ptr(out), _stream(stream)))
+    return out
+
+
+def sgm_aggregate(cost: torch.Tensor, npaths: int, p1: int, p2: int,
+                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """SGM path aggregation; returns uint16 [H][W][D]."""
+    if cost.dtype != torch.uint8 or cost.dim() != 3:
+        raise ValueError("cost must be a 3-D uint8 tensor")
+    h, w, nd = cost.shape
+    if out is None:
+        out = _empty((h, w, nd), torch.uint16, cost.device)
+    _expect(out, torch.uint16, (h, w, nd), "out")
+    _check(load_library().sgm_aggregate(_ptr(cost), w, h, nd, npaths, p1, p2, _ptr(out),
+                                        _stream(stream)))
+    return out
+
+
+def wta_lrc_work_elems(width: int, height: int) -> int:
+    return int(load_library().sgm_wta_lrc_work_elems(width, height))
+
+
+def sgm_wta_lrc(agg: torch.Tensor, lr_tolerance: int, median3x3: bool,
+                out: Optional[torch.Tensor] = None, out_right: Optional[torch.Tensor] = None,
+                work: Optional[torch.Tensor] = None, want_right: bool = False, stream=None):
+    """WTA, approximate D^R, LR check, 3x3 median.  Returns (disp, disp_right
+    or None), both uint16 [H][W], 0xFFFF = invalid."""
+    if agg.dtype != torch.uint16 or agg.dim() != 3:
+        raise ValueError("agg must be a 3-D uint16 tensor")
+    h, w, nd = agg.shape
+    dev = agg.device
+    if out is None:
+        out = _empty((h, w), torch.uint16, dev)
+    _expect(out, torch.uint16, (h, w), "out")
+    if want_right and out_right is None:
+        out_right = _empty((h, w), torch.uint16, dev)
+    if out_right is not None:
+        _expect(out_right, torch.uint16, (h, w), "out_right")
+    if work is None:
+        work = _empty((wta_lrc_work_elems(w, h),), torch.uint16, dev)
+    _check(load_library().sgm_wta_lrc(_ptr(agg), w, h, nd, lr_tolerance, int(bool(median3x3)),
+                                      _ptr(out), _ptr(out_right), _ptr(work), _stream(stream)))
+    return out, out_right
+
+
+@dataclass(frozen=True)
+class Params:
+    """Pipeline parameters (lr_tolerance < 0 skips the LR check)."""
+    win_w: int = 9
+    win_h: int = 7
+    ndisp: int = 128
+    npaths: int = 8
+    p1: int = 10
+    p2: int = 120
+    lr_tolerance: int = 1
+    median3x3: bool = True
+
+
+class StereoSGM:
+    """Device buffers for one frame shape, reused across frames; run() enqueues
+    the four ABI calls on one stream."""
+
+    def __init__(self, width: int, height: int, params: Params, device="cuda"):
+        self.width, self.height, self.params = width, height, params
+        dev = torch.device(device)
+        nd = params.ndisp
+        self.census_left = _empty((height, width), torch.uint64, dev)
+        self.census_right = _empty((height, width), torch.uint64, dev)
+        self.cost = _empty((height, width, nd), torch.uint8, dev)
+        self.agg = _empty((height, width, nd), torch.uint16, dev)
+        self.disp = _empty((height, width), torch.uint16, dev)
+        self.disp_right = _empty((height, width), torch.uint16, dev)
+        self.work = _empty((wta_lrc_work_elems(width, height),), torch.uint16, dev)
+
+    def run(self, left: torch.Tensor, right: torch.Tensor, stream=None) -> torch.Tensor:
+        p = self.params
+        sgm_census(left, p.win_w, p.win_h, out=self.census_left, width=self.width, stream=stream)
+        sgm_census(right, p.win_w, p.win_h, out=self.census_right, width=self.width, stream=stream)
+        sgm_cost(self.census_left, self.census_right, p.ndisp, out=self.cost, stream=stream)
+        sgm_aggregate(self.cost, p.npaths, p.p1, p.p2, out=self.agg, stream=stream)
+        sgm_wta_lrc(self.agg, p.lr_tolerance, p.median3x3, out=self.disp,
+                    out_right=self.disp_right, work=self.work, stream=stream)
+        return self.disp

@@ -1,0 +1,107 @@
+"""C ABI checks that need no GPU: libsgm.so loads, exports every function
+declared in include/sgm.h, and rejects bad arguments before any launch
+(every call below fails validation, so no kernel is ever enqueued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2106_07927_amd import sgm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgm.h")
+
+OK, ARG, UNSUP, ALIGN, HIP, WS = 0, -1, -2, -3, -4, -5
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sgm.LIB_PATH):
+        pytest.skip("libsgm.so not built (run python -m paper_2106_07927_amd.build)")
+    return sgm.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"sgm_census", "sgm_cost", "sgm_aggregate", "sgm_wta_lrc"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(sgm.EXPORTS) == set(names)
+
+
+def test_status_strings_and_version(lib):
+    assert lib.sgm_abi_version() == 1
+    for code in (OK, ARG, UNSUP, ALIGN, HIP, WS):
+        assert lib.sgm_status_string(code).decode().startswith("SGM_")
+    assert lib.sgm_status_string(99) == b"unknown sgm status"
+
+
+FAKE = 0x10000        # aligned, never dereferenced: validation fails first
+NULL = 0
+
+
+def P(v):
+    return ctypes.c_void_p(v)
+
+
+def test_census_validation(lib):
+    f = lib.sgm_census
+    assert f(P(NULL), 64, 64, 64, 9, 7, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 64, 64, 64, 9, 7, P(NULL), P(NULL)) == ARG
+    assert f(P(FAKE), 0, 64, 64, 9, 7, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 64, -1, 64, 9, 7, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 64, 64, 63, 9, 7, P(FAKE), P(NULL)) == ARG      # pitch < width
+    assert f(P(FAKE), 40000, 8, 40000, 9, 7, P(FAKE), P(NULL)) == ARG  # beyond the size limit
+    assert f(P(FAKE), 64, 64, 64, 7, 9, P(FAKE), P(NULL)) == UNSUP
+    assert f(P(FAKE), 64, 64, 64, 3, 3, P(FAKE), P(NULL)) == UNSUP
+    assert f(P(FAKE), 64, 64, 64, 5, 5, P(FAKE + 4), P(NULL)) == ALIGN
+
+
+def test_cost_validation(lib):
+    f = lib.sgm_cost
+    assert f(P(NULL), P(FAKE), 8, 8, 16, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 8, 8, 0, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 8, 8, 257, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 8, 8, 16, P(FAKE + 8), P(NULL)) == ALIGN
+    assert f(P(FAKE + 4), P(FAKE), 8, 8, 16, P(FAKE), P(NULL)) == ALIGN
+
+
+def test_aggregate_validation(lib):
+    f = lib.sgm_aggregate
+    assert f(P(NULL), 8, 8, 16, 8, 10, 120, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 16, 6, 10, 120, P(FAKE), P(NULL)) == ARG    # npaths
+    assert f(P(FAKE), 8, 8, 16, 8, 121, 120, P(FAKE), P(NULL)) == ARG   # p1 > p2
+    assert f(P(FAKE), 8, 8, 16, 8, -1, 120, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 16, 8, 10, 7937, P(FAKE), P(NULL)) == ARG   # 8 * (255 + p2) > 65535
+    assert f(P(FAKE), 8, 8, 16, 4, 10, 16129, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 300, 8, 10, 120, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE + 8), 8, 8, 16, 8, 10, 120, P(FAKE), P(NULL)) == ALIGN
+    assert f(P(FAKE), 8, 8, 16, 8, 10, 120, P(FAKE + 2), P(NULL)) == ALIGN
+
+
+def test_wta_lrc_validation(lib):
+    f = lib.sgm_wta_lrc
+    assert f(P(NULL), 8, 8, 16, 1, 1, P(FAKE), P(NULL), P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 16, 1, 1, P(NULL), P(NULL), P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 16, 1, 2, P(FAKE), P(NULL), P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 0, 1, 1, P(FAKE), P(NULL), P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 16, 1, 1, P(FAKE), P(NULL), P(NULL), P(NULL)) == WS
+    assert f(P(FAKE + 8), 8, 8, 16, 1, 1, P(FAKE), P(NULL), P(FAKE), P(NULL)) == ALIGN
+    assert f(P(FAKE), 8, 8, 16, 1, 1, P(FAKE + 2), P(NULL), P(FAKE), P(NULL)) == ALIGN
+    assert f(P(FAKE), 8, 8, 16, 1, 1, P(FAKE), P(FAKE + 2), P(FAKE), P(NULL)) == ALIGN
+    assert lib.sgm_wta_lrc_work_elems(10, 20) == 3 * 200
+    assert lib.sgm_wta_lrc_work_elems(0, 20) == 0
+
+
+def test_python_binding_rejects_host_tensors(lib):
+    import torch
+    img = torch.zeros(4, 4, dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        sgm.sgm_census(img, 5, 5, out=torch.zeros(4, 4, dtype=torch.uint64))
