@@ -40,6 +40,8 @@ extern "C" {
 
 #define SGM_INVALID 0xFFFFu
 #define SGM_MAX_NDISP 256
+#define SGM_MAX_SIDE 32768               /* width and height limit              */
+#define SGM_MAX_VOLUME 2147483647LL      /* width * height * ndisp limit        */
 
 typedef enum {
     SGM_OK = 0,
@@ -72,7 +74,7 @@ int32_t sgm_census(const uint8_t* img, int32_t width, int32_t height,
  *   C(x, y, d) = popcount(CL(x, y) ^ CR(x - d, y))   if x - d >= 0
  *              = 255 (0xFF, no match; Sec. 2.3.1)    otherwise
  *   census_left, census_right  uint64 [height][width], 8-byte aligned
- *   ndisp                      1 .. 256
+ *   ndisp                      1 .. 256, width*height*ndisp <= SGM_MAX_VOLUME
  *   cost_out                   uint8 [height][width][ndisp], 16-byte aligned
  * Errors: SGM_ERR_ARG, SGM_ERR_ALIGN.
  */
@@ -88,16 +90,27 @@ int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right,
  *   S_bar(p, d) = sum over the path set of L_r(p, d).
  * Path sets: npaths = 4 -> the two horizontal and the two vertical paths
  * (Sec. 3.1.4); npaths = 8 adds the four diagonals.
- *   cost     uint8 [height][width][ndisp], 16-byte aligned
- *   p1, p2   penalties with 0 <= p1 <= p2 and npaths * (255 + p2) <= 65535,
- *            so that every S_bar fits uint16 exactly
- *   agg_out  uint16 [height][width][ndisp], 16-byte aligned
- * Errors: SGM_ERR_ARG (sizes, npaths not 4/8, p1 > p2, overflow bound),
- *         SGM_ERR_ALIGN.
+ *   cost       uint8 [height][width][ndisp], 16-byte aligned
+ *   p1, p2     penalties with 0 <= p1 <= p2 and npaths * (255 + p2) <= 65535,
+ *              so that every S_bar fits uint16 exactly
+ *   agg_out    uint16 [height][width][ndisp], 16-byte aligned
+ *   work       device scratch of at least sgm_aggregate_work_bytes(...) bytes,
+ *              16-byte aligned, holding one slice per path between the path
+ *              pass and the sum; contents on return are unspecified
+ * Errors: SGM_ERR_ARG (sizes, width*height*ndisp > SGM_MAX_VOLUME, npaths
+ *         not 4/8, p1 > p2, overflow bound), SGM_ERR_WORKSPACE (work NULL or
+ *         work_bytes too small), SGM_ERR_ALIGN.
  */
 int32_t sgm_aggregate(const uint8_t* cost, int32_t width, int32_t height,
                       int32_t ndisp, int32_t npaths, int32_t p1, int32_t p2,
-                      uint16_t* agg_out, void* stream);
+                      uint16_t* agg_out, void* work, size_t work_bytes,
+                      void* stream);
+
+/* Bytes of `work` that sgm_aggregate needs: npaths slices of
+ * width*height*ndisp elements (rounded up to 256), 1 byte each when
+ * p2 <= 255, else 2.  0 on invalid sizes or penalties. */
+size_t sgm_aggregate_work_bytes(int32_t width, int32_t height, int32_t ndisp,
+                                int32_t npaths, int32_t p2);
 
 /*
  * Disparity selection and post-processing (Eq. wta, Eq. right_disparity,

@@ -1,29 +1,39 @@
 // aggregate.hip -- SGM path aggregation, Eq. (sgm_path) and Eq. (sgm_path_aggr)
 // of Ruf et al. 2021 (Sec. 2.1.2), gfx950.
 //
-// Every path direction r splits the image into independent lines (rows for
-// the horizontal paths, columns for the vertical ones, and for the diagonals
-// W "wrapped" lines that take one pixel per row and restart at the border, as
-// the paper's CUDA scheme does in Sec. 2.2.2, so every diagonal line has the
-// same length H).  One launch covers all paths of the set, each block owning
-// a run of lines of one direction.
+// Lines.  Every path direction r splits the image into independent lines:
+// rows for the horizontal paths, columns for the vertical ones, and for the
+// diagonals W "wrapped" lines that take one pixel per row and restart when
+// they cross the left/right border -- the paper's CUDA scheme (Sec. 2.2.2) --
+// so every diagonal line is H pixels long.  One launch (paths_kernel) runs
+// every direction of the set at once, each block owning a run of lines of one
+// direction; the long horizontal chains, which bound the launch, get priority.
 //
-// A line is owned by LPL consecutive lanes of a wave; each lane keeps 2*NREG
-// disparities of the line's current path vector as packed uint16 pairs in
-// NREG VGPRs.  Per pixel step:
-//   * the cost bytes of the step were loaded PF steps earlier (prefetch ring);
-//   * the state is kept normalised, N = L' - m', so the recursion reads
-//       L(d) = C(d) + min(N(d), min(N(d-1), N(d+1)) + P1, P2);
-//     min(N(d-1), N(d+1)) comes from Q_k = min(P_k, P_k+1) and one alignbit per
-//     register, with a single DPP lane shift each way per step;
-//   * m = min_d L(d) is a per-lane v_pk_min_u16 tree followed by a DPP
-//     all-reduce over the line's lanes;
-//   * L is added into S_bar with 32-bit atomics on packed pairs.  They are
-//     exact: no partial sum exceeds 16 bits (the ABI checks
-//     npaths * (255 + P2) <= 65535), so no carry crosses a half, and integer
-//     addition makes the result independent of the order.
-// Disparities beyond D (padding lanes) hold 0x7FFF, which never wins a
-// minimum and, as a neighbour, never beats the P2 term.
+// Lanes.  A line is owned by LPL consecutive lanes; each lane keeps 2*NREG
+// disparities of the path vector as packed uint16 pairs.  The state is kept
+// normalised, N = L' - min_d L', so one step reads
+//     L(d) = C(d) + min(N(d), min(N(d-1), N(d+1)) + P1, P2);
+// min(N(d-1), N(d+1)) comes from Q_k = min(P_k, P_k+1) and one alignbit per
+// register, with one DPP lane shift each way per step; min_d L is a
+// v_pk_min_u16 tree plus a DPP / permlane all-reduce over the line's lanes.
+// Disparities beyond D (padding) hold 0x7FFF: never a minimum, and as a
+// neighbour never below the P2 term.
+//
+// Memory.  On this GPU family one counter tracks both loads and stores, so a
+// loop that prefetches while it stores would wait for every store each step.
+// The loop therefore runs in chunks of K steps: at a chunk boundary it waits
+// once, issues the loads of the next chunk, and computes the K steps from
+// registers.  No branch guards a load (positions past a line's end are
+// clamped to its last pixel).
+//
+// Sum over paths.  Paths visit a pixel in different orders, so their values
+// meet in memory: each path writes its own slice, then merge_kernel forms
+// S_bar.  With P2 <= 255 a path writes only its penalty part
+//     A_r(p, d) = L_r(p, d) - C(p, d) = min(N(d), N(d +- 1) + P1, P2) in [0, P2]
+// as uint8 (exact), and S_bar = R * C + sum_r A_r; otherwise it writes L_r as
+// uint16 and S_bar = sum_r L_r.  32-bit atomics on packed pairs would also be
+// exact, but device-wide atomics run an order of magnitude slower here than
+// the two plain passes.
 #include "sgm_internal.h"
 
 namespace sgm {
@@ -33,6 +43,8 @@ constexpr uint32_t kBig = 0x7FFFu;
 constexpr uint32_t kBig2 = 0x7FFF7FFFu;
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
+
+enum Kind : int { kHorizontal = 0, kVertical = 1, kDiagonal = 2 };
 
 struct DirTask {
     int dx, dy;      // step r: the predecessor of p is p - r
@@ -46,7 +58,7 @@ struct DirTable {
     int ndir;
 };
 
-// ---- cross-lane helpers for groups of 32 and 64 lanes ---------------------
+// ---- cross-lane helpers for lines of up to 64 lanes -----------------------
 template <int GROUP>
 __device__ __forceinline__ uint32_t line_min(uint32_t v) {
     if constexpr (GROUP <= 16) {
@@ -69,8 +81,9 @@ __device__ __forceinline__ uint32_t line_next(uint32_t v, uint32_t edge, bool la
     if constexpr (GROUP <= 16) {
         return group_next<GROUP>(v, edge, last);
     } else {
-        uint32_t r = (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xF, 0xF, false);
-        return last ? edge : r;   // wave_shl:1
+        const uint32_t r = (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xF, 0xF, false);
+        if constexpr (GROUP == 64) return r;        // wave_shl:1, lane 63 keeps `edge`
+        else return last ? edge : r;
     }
 }
 
@@ -79,12 +92,13 @@ __device__ __forceinline__ uint32_t line_prev(uint32_t v, uint32_t edge, bool fi
     if constexpr (GROUP <= 16) {
         return group_prev<GROUP>(v, edge, first);
     } else {
-        uint32_t r = (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xF, 0xF, false);
-        return first ? edge : r;  // wave_shr:1
+        const uint32_t r = (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xF, 0xF, false);
+        if constexpr (GROUP == 64) return r;        // wave_shr:1, lane 0 keeps `edge`
+        else return first ? edge : r;
     }
 }
 
-// ---- cost vector of one lane for one pixel: 2*NREG bytes ------------------
+// ---- cost bytes of one lane for one pixel: 2*NREG bytes --------------------
 template <int NREG>
 struct CostVec {
     static constexpr int kWords = (NREG + 1) / 2;
@@ -92,35 +106,32 @@ struct CostVec {
 };
 
 template <int NREG, bool ALIGNED>
-__device__ __forceinline__ CostVec<NREG> load_cost(const uint8_t* __restrict__ cost,
-                                                   size_t off, int d0, int ndisp) {
+__device__ __forceinline__ CostVec<NREG> load_cost(const uint8_t* __restrict__ cost, uint32_t off,
+                                                   int d0, int ndisp) {
     CostVec<NREG> c;
-#pragma unroll
-    for (int i = 0; i < CostVec<NREG>::kWords; ++i) c.w[i] = 0;
     if constexpr (ALIGNED) {
-        if (d0 < ndisp) {
-            const uint8_t* p = cost + off;
-            if constexpr (NREG == 1) {
-                c.w[0] = *reinterpret_cast<const uint16_t*>(p);
-            } else if constexpr (NREG == 2) {
-                c.w[0] = *reinterpret_cast<const uint32_t*>(p);
-            } else if constexpr (NREG == 4) {
-                const uint2 v = *reinterpret_cast<const uint2*>(p);
-                c.w[0] = v.x;
-                c.w[1] = v.y;
-            } else {
-                const uint4 v = *reinterpret_cast<const uint4*>(p);
-                c.w[0] = v.x;
-                c.w[1] = v.y;
-                c.w[2] = v.z;
-                c.w[3] = v.w;
-            }
+        const uint8_t* p = cost + off;
+        if constexpr (NREG == 1) {
+            c.w[0] = *reinterpret_cast<const uint16_t*>(p);
+        } else if constexpr (NREG == 2) {
+            c.w[0] = *reinterpret_cast<const uint32_t*>(p);
+        } else if constexpr (NREG == 4) {
+            const uint2 v = *reinterpret_cast<const uint2*>(p);
+            c.w[0] = v.x;
+            c.w[1] = v.y;
+        } else {
+            const uint4 v = *reinterpret_cast<const uint4*>(p);
+            c.w[0] = v.x;
+            c.w[1] = v.y;
+            c.w[2] = v.z;
+            c.w[3] = v.w;
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < 2 * NREG; ++e) {
+        for (int i = 0; i < CostVec<NREG>::kWords; ++i) c.w[i] = 0;
+#pragma unroll
+        for (int e = 0; e < 2 * NREG; ++e)
             if (d0 + e < ndisp) c.w[e >> 2] |= (uint32_t)cost[off + e] << (8 * (e & 3));
-        }
     }
     return c;
 }
@@ -128,175 +139,269 @@ __device__ __forceinline__ CostVec<NREG> load_cost(const uint8_t* __restrict__ c
 // bytes 2k, 2k+1 of the vector, zero-extended into a packed pair
 template <int NREG>
 __device__ __forceinline__ uint32_t cost_pair(const CostVec<NREG>& c, int k) {
-    const uint32_t sel = (k & 1) ? 0x0c030c02u : 0x0c010c00u;
-    return __builtin_amdgcn_perm(0u, c.w[k >> 1], sel);
+    return __builtin_amdgcn_perm(0u, c.w[k >> 1], (k & 1) ? 0x0c030c02u : 0x0c010c00u);
 }
 
-template <int NREG, bool ALIGNED>
-__device__ __forceinline__ void add_atomic(uint16_t* __restrict__ agg, size_t off, int d0,
-                                           int ndisp, const uint32_t (&L)[NREG]) {
-    if constexpr (ALIGNED) {
-        if (d0 < ndisp) {
-            uint32_t* p = reinterpret_cast<uint32_t*>(agg + off);
+// Writes the step's output of one lane: penalty bytes (U8) or path values.
+template <int NREG, bool ALIGNED, bool U8>
+__device__ __forceinline__ void store_out(void* __restrict__ slice, uint32_t off, int d0, int ndisp,
+                                          const uint32_t (&A)[NREG], const uint32_t (&L)[NREG]) {
+    if constexpr (U8) {
+        uint8_t* p = static_cast<uint8_t*>(slice) + off;
+        if constexpr (ALIGNED) {
+            if constexpr (NREG == 1) {
+                *reinterpret_cast<uint16_t*>(p) = (uint16_t)__builtin_amdgcn_perm(0u, A[0], 0x0c0c0200u);
+            } else if constexpr (NREG == 2) {
+                *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(A[1], A[0], 0x06040200u);
+            } else if constexpr (NREG == 4) {
+                *reinterpret_cast<uint2*>(p) = make_uint2(__builtin_amdgcn_perm(A[1], A[0], 0x06040200u),
+                                                          __builtin_amdgcn_perm(A[3], A[2], 0x06040200u));
+            } else {
+                *reinterpret_cast<uint4*>(p) = make_uint4(__builtin_amdgcn_perm(A[1], A[0], 0x06040200u),
+                                                          __builtin_amdgcn_perm(A[3], A[2], 0x06040200u),
+                                                          __builtin_amdgcn_perm(A[5], A[4], 0x06040200u),
+                                                          __builtin_amdgcn_perm(A[7], A[6], 0x06040200u));
+            }
+        } else {
 #pragma unroll
-            for (int k = 0; k < NREG; ++k) atomicAdd(p + k, L[k]);
+            for (int e = 0; e < 2 * NREG; ++e)
+                if (d0 + e < ndisp) p[e] = (uint8_t)((e & 1) ? (A[e >> 1] >> 16) : A[e >> 1]);
         }
     } else {
+        uint16_t* p = static_cast<uint16_t*>(slice) + off;
+        if constexpr (ALIGNED) {
+            uint32_t* q = reinterpret_cast<uint32_t*>(p);
 #pragma unroll
-        for (int e = 0; e < 2 * NREG; ++e) {
-            if (d0 + e < ndisp) {
-                const size_t idx = off + e;
-                const uint32_t v = (e & 1) ? (L[e >> 1] >> 16) : (L[e >> 1] & 0xFFFFu);
-                uint32_t* word = reinterpret_cast<uint32_t*>(agg) + (idx >> 1);
-                atomicAdd(word, v << (16 * (idx & 1)));
-            }
+            for (int k = 0; k < NREG; ++k) q[k] = L[k];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 2 * NREG; ++e)
+                if (d0 + e < ndisp) p[e] = (uint16_t)((e & 1) ? (L[e >> 1] >> 16) : L[e >> 1]);
         }
     }
 }
 
 // One wave's lines of one direction, the whole way along.
-template <int NREG, int LPL, int PF, bool ALIGNED>
-__device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost,
-                                          uint16_t* __restrict__ agg, int width, int height,
-                                          int ndisp, uint32_t p1x2, uint32_t p2x2,
-                                          const DirTask& task, int wave_in_dir) {
+template <int KIND, int NREG, int LPL, int K, bool ALIGNED, bool PADDED, bool U8>
+__device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void* __restrict__ slice,
+                                          int width, int height, int ndisp, uint32_t p1x2,
+                                          uint32_t p2x2, const DirTask& task, int wave_in_dir) {
     constexpr int DPL = 2 * NREG;
     constexpr int LPW = 64 / LPL;
     const int lane = threadIdx.x & 63;
     const int sub = lane % LPL;
     const int line = wave_in_dir * LPW + lane / LPL;
-    const bool valid = line < task.nlines;
-    const int lc = valid ? line : task.nlines - 1;
-    const int d0 = sub * DPL;
+    const bool line_ok = line < task.nlines;
+    const int lc = line_ok ? line : task.nlines - 1;
+    const bool d_ok = sub * DPL < ndisp;
+    const int d0 = d_ok ? sub * DPL : 0;             // padding lanes read d = 0
+    const bool write = line_ok && d_ok;
     const bool first_lane = sub == 0;
     const bool last_lane = sub == LPL - 1;
     const int dx = task.dx, dy = task.dy;
-    const bool diag = dx != 0 && dy != 0;
+    const int nsteps = task.nsteps;
+    const uint32_t pix_bytes = (uint32_t)ndisp;
 
-    // padding: 0x7FFF in every element with d >= D
     uint32_t pad[NREG];
 #pragma unroll
     for (int k = 0; k < NREG; ++k) {
-        const uint32_t lo = (d0 + 2 * k < ndisp) ? 0u : kBig;
-        const uint32_t hi = (d0 + 2 * k + 1 < ndisp) ? 0u : kBig;
+        const uint32_t lo = (sub * DPL + 2 * k < ndisp) ? 0u : kBig;
+        const uint32_t hi = (sub * DPL + 2 * k + 1 < ndisp) ? 0u : kBig;
         pad[k] = lo | (hi << 16);
     }
 
-    // start pixel of the line
+    // current pixel (x, y) and the look-ahead pixel of the prefetch
     int x, y;
-    if (dy == 0) {
+    if constexpr (KIND == kHorizontal) {
         y = lc;
         x = dx > 0 ? 0 : width - 1;
     } else {
         x = lc;
         y = dy > 0 ? 0 : height - 1;
     }
-    int xa = x, ya = y;   // look-ahead position for the prefetch
-    const int nsteps = task.nsteps;
-    auto advance = [&](int& px, int& py) {
+    const int restart_x = dx > 0 ? 0 : width - 1;
+    int xa = x, ya = y, sa = 0;
+    auto step_pos = [&](int& px, int& py) {
         px += dx;
         py += dy;
-        if (diag) {
-            if (px == width) px = 0;
-            else if (px < 0) px = width - 1;
+        if constexpr (KIND == kDiagonal) {
+            px = (px == width) ? 0 : px;
+            px = (px < 0) ? width - 1 : px;
         }
     };
+    auto fetch = [&]() {
+        const CostVec<NREG> c = load_cost<NREG, ALIGNED>(
+            cost, ((uint32_t)ya * (uint32_t)width + (uint32_t)xa) * pix_bytes + (uint32_t)d0, d0, ndisp);
+        if (sa + 1 < nsteps) step_pos(xa, ya);     // stay on the last pixel past the end
+        ++sa;
+        return c;
+    };
 
-    CostVec<NREG> ring[PF];
+    CostVec<NREG> nxt[K];
 #pragma unroll
-    for (int j = 0; j < PF; ++j) {
-        if (j < nsteps) ring[j] = load_cost<NREG, ALIGNED>(cost, ((size_t)ya * width + xa) * ndisp + d0, d0, ndisp);
-        advance(xa, ya);
-    }
+    for (int j = 0; j < K; ++j) nxt[j] = fetch();
 
     uint32_t P[NREG];
 #pragma unroll
     for (int k = 0; k < NREG; ++k) P[k] = pad[k];
-    const int restart_x = dx > 0 ? 0 : width - 1;
 
-    for (int s0 = 0; s0 < nsteps; s0 += PF) {
+    const int nchunks = (nsteps + K - 1) / K;
+    for (int chunk = 0; chunk < nchunks; ++chunk) {
+        CostVec<NREG> cur[K];
 #pragma unroll
-        for (int j = 0; j < PF; ++j) {
-            const int s = s0 + j;
-            if (s >= nsteps) break;
-            const CostVec<NREG> c = ring[j];
-            if (s + PF < nsteps) {
-                ring[j] = load_cost<NREG, ALIGNED>(cost, ((size_t)ya * width + xa) * ndisp + d0, d0, ndisp);
-            }
-            advance(xa, ya);
-
-            // a diagonal line restarts where it wrapped to the other border
-            if (diag && s > 0 && x == restart_x) {
+        for (int j = 0; j < K; ++j) cur[j] = nxt[j];
 #pragma unroll
-                for (int k = 0; k < NREG; ++k) P[k] = pad[k];
+        for (int j = 0; j < K; ++j) nxt[j] = fetch();
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int s = chunk * K + j;
+            if constexpr (KIND == kDiagonal) {
+                // a wrapped line restarts where it re-enters at the other border
+                const bool restart = s > 0 && x == restart_x;
+#pragma unroll
+                for (int k = 0; k < NREG; ++k) P[k] = restart ? pad[k] : P[k];
             }
-
-            // min(N(d-1), N(d+1)) for every register
             uint32_t Q[NREG];
-            const uint32_t nxt = line_next<LPL>(P[0], kBig2, last_lane);
+            const uint32_t nxt0 = line_next<LPL>(P[0], kBig2, last_lane);
 #pragma unroll
             for (int k = 0; k + 1 < NREG; ++k) Q[k] = pk_min(P[k], P[k + 1]);
-            Q[NREG - 1] = pk_min(P[NREG - 1], nxt);
+            Q[NREG - 1] = pk_min(P[NREG - 1], nxt0);
             const uint32_t qprev = line_prev<LPL>(Q[NREG - 1], P[0], first_lane);
 
-            uint32_t L[NREG];
+            uint32_t A[NREG], L[NREG];
 #pragma unroll
             for (int k = 0; k < NREG; ++k) {
-                const uint32_t M = pk_shift_in(Q[k], k == 0 ? qprev : Q[k - 1]);
-                uint32_t a = pk_add(M, p1x2);
-                a = pk_min(a, P[k]);
-                a = pk_min(a, p2x2);
-                a = pk_add(a, cost_pair<NREG>(c, k));
-                if (ALIGNED ? (LPL * DPL > ndisp) : true) a = pk_max(a, pad[k]);
-                L[k] = a;
+                uint32_t a = pk_add(pk_shift_in(Q[k], k == 0 ? qprev : Q[k - 1]), p1x2);
+                a = pk_min(pk_min(a, P[k]), p2x2);
+                A[k] = a;
+                uint32_t l = pk_add(a, cost_pair<NREG>(cur[j], k));
+                if constexpr (PADDED) l = pk_max(l, pad[k]);
+                L[k] = l;
             }
-
             uint32_t mm = L[0];
 #pragma unroll
             for (int k = 1; k < NREG; ++k) mm = pk_min(mm, L[k]);
-            uint32_t m = min(mm & 0xFFFFu, mm >> 16);
-            m = line_min<LPL>(m);
+            const uint32_t m = line_min<LPL>(min(mm & 0xFFFFu, mm >> 16));
             const uint32_t m2 = pk_splat(m);
 
-            if (valid) add_atomic<NREG, ALIGNED>(agg, ((size_t)y * width + x) * ndisp + d0, d0, ndisp, L);
-
+            if (write && s < nsteps)
+                store_out<NREG, ALIGNED, U8>(slice, ((uint32_t)y * (uint32_t)width + (uint32_t)x) * pix_bytes + (uint32_t)d0,
+                                             d0, ndisp, A, L);
 #pragma unroll
             for (int k = 0; k < NREG; ++k) P[k] = pk_sub(L[k], m2);
-            advance(x, y);
+            if (s + 1 < nsteps) step_pos(x, y);
         }
     }
 }
 
-template <int NREG_H, int LPL_H, int NREG_O, int LPL_O, int PF, bool AL_H, bool AL_O>
-__global__ __launch_bounds__(kThreads) void aggregate_kernel(const uint8_t* __restrict__ cost,
-                                                             uint16_t* __restrict__ agg,
-                                                             int width, int height, int ndisp,
-                                                             uint32_t p1x2, uint32_t p2x2,
-                                                             DirTable tab) {
+template <int NH, int LH, int NO, int LO, bool ALH, bool PDH, bool ALO, bool PDO, bool U8>
+__global__ __launch_bounds__(kThreads) void paths_kernel(const uint8_t* __restrict__ cost,
+                                                         uint8_t* __restrict__ slices,
+                                                         size_t slice_elems, int width, int height,
+                                                         int ndisp, uint32_t p1x2, uint32_t p2x2,
+                                                         DirTable tab) {
+    // steps per chunk: enough to cover a memory round trip, few enough to
+    // keep two chunks of cost bytes in registers
+    constexpr int KH = NH == 1 ? 32 : 16;
+    constexpr int KO = NO <= 4 ? 16 : 8;
     int di = 0;
 #pragma unroll
     for (int i = 1; i < 8; ++i)
         if (i < tab.ndir && (int)blockIdx.x >= tab.t[i].block0) di = i;
     const DirTask task = tab.t[di];
     const int wave_in_dir = ((int)blockIdx.x - task.block0) * kWaves + (int)(threadIdx.x >> 6);
+    void* slice = slices + (size_t)di * slice_elems * (U8 ? 1 : 2);
     if (task.dy == 0) {
-        __builtin_amdgcn_s_setprio(2);   // the long horizontal chains go first
-        run_lines<NREG_H, LPL_H, PF, AL_H>(cost, agg, width, height, ndisp, p1x2, p2x2, task, wave_in_dir);
+        __builtin_amdgcn_s_setprio(2);
+        run_lines<kHorizontal, NH, LH, KH, ALH, PDH, U8>(cost, slice, width, height, ndisp, p1x2, p2x2,
+                                                         task, wave_in_dir);
+    } else if (task.dx == 0) {
+        run_lines<kVertical, NO, LO, KO, ALO, PDO, U8>(cost, slice, width, height, ndisp, p1x2, p2x2,
+                                                       task, wave_in_dir);
     } else {
-        run_lines<NREG_O, LPL_O, PF, AL_O>(cost, agg, width, height, ndisp, p1x2, p2x2, task, wave_in_dir);
+        run_lines<kDiagonal, NO, LO, KO, ALO, PDO, U8>(cost, slice, width, height, ndisp, p1x2, p2x2,
+                                                       task, wave_in_dir);
     }
 }
 
-__global__ __launch_bounds__(256) void fill_zero_kernel(uint4* __restrict__ p, size_t n16,
-                                                        uint16_t* __restrict__ tail, size_t ntail) {
+// S_bar = R * C + sum_r A_r over uint8 penalty slices (slice r starts at
+// r * stride), 16 elements per thread and iteration.  Bytes are split into
+// even/odd 16-bit lanes so that plain 32-bit adds accumulate two sums per
+// register without carries.
+__global__ __launch_bounds__(256) void merge_u8_kernel(const uint8_t* __restrict__ cost,
+                                                       const uint8_t* __restrict__ slices,
+                                                       size_t n, size_t stride_elems, int npaths,
+                                                       uint16_t* __restrict__ agg) {
+    const size_t n16 = n / 16;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-        p[i] = make_uint4(0, 0, 0, 0);
-    if (blockIdx.x == 0)
-        for (size_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+        const uint4 c = reinterpret_cast<const uint4*>(cost)[i];
+        uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+        uint32_t ev[4], od[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ev[q] = (cw[q] & 0x00FF00FFu) * (uint32_t)npaths;
+            od[q] = ((cw[q] >> 8) & 0x00FF00FFu) * (uint32_t)npaths;
+        }
+        for (int r = 0; r < npaths; ++r) {
+            const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * stride_elems)[i];
+            const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ev[q] += aw[q] & 0x00FF00FFu;
+                od[q] += (aw[q] >> 8) & 0x00FF00FFu;
+            }
+        }
+        // interleave back: element order e0 o0 e1 o1 per 32-bit source word
+        uint4 lo, hi;
+        lo.x = __builtin_amdgcn_perm(od[0], ev[0], 0x05040100u);
+        lo.y = __builtin_amdgcn_perm(od[0], ev[0], 0x07060302u);
+        lo.z = __builtin_amdgcn_perm(od[1], ev[1], 0x05040100u);
+        lo.w = __builtin_amdgcn_perm(od[1], ev[1], 0x07060302u);
+        hi.x = __builtin_amdgcn_perm(od[2], ev[2], 0x05040100u);
+        hi.y = __builtin_amdgcn_perm(od[2], ev[2], 0x07060302u);
+        hi.z = __builtin_amdgcn_perm(od[3], ev[3], 0x05040100u);
+        hi.w = __builtin_amdgcn_perm(od[3], ev[3], 0x07060302u);
+        reinterpret_cast<uint4*>(agg)[2 * i] = lo;
+        reinterpret_cast<uint4*>(agg)[2 * i + 1] = hi;
+    }
+    // tail
+    if (blockIdx.x == 0) {
+        for (size_t e = n16 * 16 + threadIdx.x; e < n; e += blockDim.x) {
+            uint32_t s = (uint32_t)cost[e] * (uint32_t)npaths;
+            for (int r = 0; r < npaths; ++r) s += slices[(size_t)r * stride_elems + e];
+            agg[e] = (uint16_t)s;
+        }
+    }
 }
 
-// Lane layout per disparity range: (NREG, LPL) so that LPL * 2 * NREG >= D.
+// S_bar = sum_r L_r over uint16 path slices.
+__global__ __launch_bounds__(256) void merge_u16_kernel(const uint16_t* __restrict__ slices,
+                                                        size_t n, size_t stride_elems, int npaths,
+                                                        uint16_t* __restrict__ agg) {
+    const size_t n8 = n / 8;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) {
+        uint4 s = reinterpret_cast<const uint4*>(slices)[i];
+        for (int r = 1; r < npaths; ++r) {
+            const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * stride_elems)[i];
+            s.x = pk_add(s.x, a.x);
+            s.y = pk_add(s.y, a.y);
+            s.z = pk_add(s.z, a.z);
+            s.w = pk_add(s.w, a.w);
+        }
+        reinterpret_cast<uint4*>(agg)[i] = s;
+    }
+    if (blockIdx.x == 0) {
+        for (size_t e = n8 * 8 + threadIdx.x; e < n; e += blockDim.x) {
+            uint32_t s = 0;
+            for (int r = 0; r < npaths; ++r) s += slices[(size_t)r * stride_elems + e];
+            agg[e] = (uint16_t)s;
+        }
+    }
+}
+
+// Lane layout per disparity range: (NREG, LPL) with LPL * 2 * NREG >= D.
 struct Layout {
     int nreg, lpl;
 };
@@ -323,43 +428,46 @@ Layout layout_horizontal(int ndisp) {
     return {2, 64};
 }
 
-template <int NREG_H, int LPL_H, int NREG_O, int LPL_O>
-hipError_t launch_variant(const uint8_t* cost, int width, int height, int ndisp,
-                          uint32_t p1x2, uint32_t p2x2, uint16_t* agg, const DirTable& tab,
-                          int nblocks, hipStream_t stream) {
-    constexpr int PF = 4;
-    const bool al_h = ndisp % (2 * NREG_H) == 0;
-    const bool al_o = ndisp % (2 * NREG_O) == 0;
-#define SGM_AGG_LAUNCH(AH, AO)                                                                  \
-    aggregate_kernel<NREG_H, LPL_H, NREG_O, LPL_O, PF, AH, AO>                                   \
-        <<<nblocks, kThreads, 0, stream>>>(cost, agg, width, height, ndisp, p1x2, p2x2, tab)
-    if (al_h && al_o) SGM_AGG_LAUNCH(true, true);
-    else if (al_h) SGM_AGG_LAUNCH(true, false);
-    else if (al_o) SGM_AGG_LAUNCH(false, true);
-    else SGM_AGG_LAUNCH(false, false);
-#undef SGM_AGG_LAUNCH
+template <int NH, int LH, int NO, int LO, bool U8>
+hipError_t launch_paths(const uint8_t* cost, uint8_t* slices, size_t n, int width, int height,
+                        int ndisp, uint32_t p1x2, uint32_t p2x2, const DirTable& tab, int nblocks,
+                        hipStream_t stream) {
+    const bool alh = ndisp % (2 * NH) == 0;
+    const bool alo = ndisp % (2 * NO) == 0;
+    const bool pdh = LH * 2 * NH > ndisp;
+    const bool pdo = LO * 2 * NO > ndisp;
+#define SGM_PATHS(A, B, C, D)                                                                     \
+    paths_kernel<NH, LH, NO, LO, A, B, C, D, U8>                                                  \
+        <<<nblocks, kThreads, 0, stream>>>(cost, slices, n, width, height, ndisp, p1x2, p2x2, tab)
+    if (alh && alo) {
+        if (!pdh && !pdo) SGM_PATHS(true, false, true, false);
+        else SGM_PATHS(true, true, true, true);
+    } else {
+        SGM_PATHS(false, true, false, true);
+    }
+#undef SGM_PATHS
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_aggregate(const uint8_t* cost, int width, int height, int ndisp,
-                            int npaths, int p1, int p2, uint16_t* agg, hipStream_t stream) {
-    // S_bar starts at zero; the paths add into it.
+// Slices start on 256-element boundaries so every vector access is aligned.
+size_t aggregate_slice_elems(int width, int height, int ndisp) {
     const size_t n = (size_t)width * height * ndisp;
-    const size_t n16 = n / 8;
-    {
-        const int blocks = (int)std::min<size_t>((n16 + 255) / 256 + 1, 4096);
-        fill_zero_kernel<<<blocks, 256, 0, stream>>>(reinterpret_cast<uint4*>(agg), n16,
-                                                    agg + n16 * 8, n - n16 * 8);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    return (n + 255) / 256 * 256;
+}
 
+size_t aggregate_work_bytes(int width, int height, int ndisp, int npaths, int p2) {
+    return (size_t)npaths * aggregate_slice_elems(width, height, ndisp) * (p2 <= 255 ? 1 : 2);
+}
+
+hipError_t launch_aggregate(const uint8_t* cost, int width, int height, int ndisp, int npaths,
+                            int p1, int p2, uint16_t* agg, void* work, hipStream_t stream) {
     static const int kDirs[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1},
                                     {1, 1}, {-1, 1}, {1, -1}, {-1, -1}};
     const Layout lh = layout_horizontal(ndisp);
     const Layout lo = layout_other(ndisp);
+    // horizontal directions first: their blocks are dispatched first
     DirTable tab{};
     int nblocks = 0;
     tab.ndir = npaths;
@@ -377,11 +485,18 @@ hipError_t launch_aggregate(const uint8_t* cost, int width, int height, int ndis
     }
     const uint32_t p1x2 = pk_splat((uint32_t)p1);
     const uint32_t p2x2 = pk_splat((uint32_t)p2);
+    const size_t n = (size_t)width * height * ndisp;
+    const size_t stride = aggregate_slice_elems(width, height, ndisp);
+    const bool u8 = p2 <= 255;
+    uint8_t* slices = static_cast<uint8_t*>(work);
 
-#define SGM_AGG_CASE(NH, LH, NO, LO)                                                          \
-    if (lh.nreg == NH && lh.lpl == LH && lo.nreg == NO && lo.lpl == LO)                      \
-        return launch_variant<NH, LH, NO, LO>(cost, width, height, ndisp, p1x2, p2x2, agg,   \
-                                              tab, nblocks, stream);
+    hipError_t e = hipErrorInvalidValue;
+#define SGM_AGG_CASE(NH, LH, NO, LO)                                                             \
+    if (lh.nreg == NH && lh.lpl == LH && lo.nreg == NO && lo.lpl == LO)                         \
+        e = u8 ? launch_paths<NH, LH, NO, LO, true>(cost, slices, stride, width, height, ndisp,   \
+                                                    p1x2, p2x2, tab, nblocks, stream)             \
+               : launch_paths<NH, LH, NO, LO, false>(cost, slices, stride, width, height, ndisp,  \
+                                                     p1x2, p2x2, tab, nblocks, stream);
     SGM_AGG_CASE(1, 1, 1, 1)
     SGM_AGG_CASE(1, 2, 2, 1)
     SGM_AGG_CASE(1, 4, 4, 1)
@@ -391,7 +506,12 @@ hipError_t launch_aggregate(const uint8_t* cost, int width, int height, int ndis
     SGM_AGG_CASE(1, 64, 4, 16)
     SGM_AGG_CASE(2, 64, 8, 16)
 #undef SGM_AGG_CASE
-    return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+
+    const int blocks = (int)std::min<size_t>((n / 16 + 255) / 256 + 1, 8192);
+    if (u8) merge_u8_kernel<<<blocks, 256, 0, stream>>>(cost, slices, n, stride, npaths, agg);
+    else merge_u16_kernel<<<blocks, 256, 0, stream>>>(reinterpret_cast<const uint16_t*>(slices), n, stride, npaths, agg);
+    return hipGetLastError();
 }
 
 }  // namespace sgm

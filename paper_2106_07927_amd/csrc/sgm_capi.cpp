@@ -19,6 +19,20 @@ bool bad_size(int32_t width, int32_t height) {
     return width < 1 || height < 1 || width > kMaxSide || height > kMaxSide;
 }
 
+// volumes are addressed with 32-bit element offsets inside the kernels
+bool bad_volume(int32_t width, int32_t height, int32_t ndisp) {
+    return ndisp < 1 || ndisp > SGM_MAX_NDISP ||
+           (int64_t)width * height * ndisp > (int64_t)SGM_MAX_VOLUME;
+}
+
+// P1 <= P2 makes the four-term recursion exact; the bound keeps every S_bar
+// inside uint16
+bool bad_penalties(int32_t npaths, int32_t p1, int32_t p2) {
+    if (npaths != 4 && npaths != 8) return true;
+    if (p1 < 0 || p2 < p1) return true;
+    return (int64_t)npaths * (255 + (int64_t)p2) > 65535;
+}
+
 int32_t hip_status(hipError_t e) {
     if (e == hipSuccess) return SGM_OK;
     g_last_hip_error = (int32_t)e;
@@ -31,7 +45,7 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 extern "C" {
 
-int32_t sgm_abi_version(void) { return 1; }
+int32_t sgm_abi_version(void) { return 2; }
 
 const char* sgm_status_string(int32_t status) {
     switch (status) {
@@ -59,23 +73,30 @@ int32_t sgm_census(const uint8_t* img, int32_t width, int32_t height, int32_t pi
 int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right, int32_t width,
                  int32_t height, int32_t ndisp, uint8_t* cost_out, void* stream) {
     if (!census_left || !census_right || !cost_out || bad_size(width, height)) return SGM_ERR_ARG;
-    if (ndisp < 1 || ndisp > SGM_MAX_NDISP) return SGM_ERR_ARG;
+    if (bad_volume(width, height, ndisp)) return SGM_ERR_ARG;
     if (!aligned(census_left, 8) || !aligned(census_right, 8) || !aligned(cost_out, 16))
         return SGM_ERR_ALIGN;
     return hip_status(sgm::launch_cost(census_left, census_right, width, height, ndisp, cost_out,
                                        as_stream(stream)));
 }
 
+size_t sgm_aggregate_work_bytes(int32_t width, int32_t height, int32_t ndisp, int32_t npaths,
+                                int32_t p2) {
+    if (bad_size(width, height) || bad_volume(width, height, ndisp) || bad_penalties(npaths, 0, p2))
+        return 0;
+    return sgm::aggregate_work_bytes(width, height, ndisp, npaths, p2);
+}
+
 int32_t sgm_aggregate(const uint8_t* cost, int32_t width, int32_t height, int32_t ndisp,
-                      int32_t npaths, int32_t p1, int32_t p2, uint16_t* agg_out, void* stream) {
+                      int32_t npaths, int32_t p1, int32_t p2, uint16_t* agg_out, void* work,
+                      size_t work_bytes, void* stream) {
     if (!cost || !agg_out || bad_size(width, height)) return SGM_ERR_ARG;
-    if (ndisp < 1 || ndisp > SGM_MAX_NDISP) return SGM_ERR_ARG;
-    if (npaths != 4 && npaths != 8) return SGM_ERR_ARG;
-    if (p1 < 0 || p2 < p1) return SGM_ERR_ARG;
-    if ((int64_t)npaths * (255 + (int64_t)p2) > 65535) return SGM_ERR_ARG;
-    if (!aligned(cost, 16) || !aligned(agg_out, 16)) return SGM_ERR_ALIGN;
+    if (bad_volume(width, height, ndisp) || bad_penalties(npaths, p1, p2)) return SGM_ERR_ARG;
+    if (!work || work_bytes < sgm::aggregate_work_bytes(width, height, ndisp, npaths, p2))
+        return SGM_ERR_WORKSPACE;
+    if (!aligned(cost, 16) || !aligned(agg_out, 16) || !aligned(work, 16)) return SGM_ERR_ALIGN;
     return hip_status(sgm::launch_aggregate(cost, width, height, ndisp, npaths, p1, p2, agg_out,
-                                            as_stream(stream)));
+                                            work, as_stream(stream)));
 }
 
 size_t sgm_wta_lrc_work_elems(int32_t width, int32_t height) {
@@ -87,7 +108,7 @@ int32_t sgm_wta_lrc(const uint16_t* agg, int32_t width, int32_t height, int32_t 
                     int32_t lr_tolerance, int32_t median3x3, uint16_t* disp_out,
                     uint16_t* disp_right_out, uint16_t* work, void* stream) {
     if (!agg || !disp_out || bad_size(width, height)) return SGM_ERR_ARG;
-    if (ndisp < 1 || ndisp > SGM_MAX_NDISP) return SGM_ERR_ARG;
+    if (bad_volume(width, height, ndisp)) return SGM_ERR_ARG;
     if (median3x3 != 0 && median3x3 != 1) return SGM_ERR_ARG;
     if (!work) return SGM_ERR_WORKSPACE;
     if (!aligned(agg, 16) || !aligned(disp_out, 4) || !aligned(work, 4) ||

@@ -90,8 +90,10 @@ hipError_t launch_census(const uint8_t* img, int width, int height, int pitch,
                          int win_w, int win_h, uint64_t* out, hipStream_t stream);
 hipError_t launch_cost(const uint64_t* cl, const uint64_t* cr, int width, int height,
                        int ndisp, uint8_t* cost, hipStream_t stream);
+size_t aggregate_work_bytes(int width, int height, int ndisp, int npaths, int p2);
 hipError_t launch_aggregate(const uint8_t* cost, int width, int height, int ndisp,
-                            int npaths, int p1, int p2, uint16_t* agg, hipStream_t stream);
+                            int npaths, int p1, int p2, uint16_t* agg, void* work,
+                            hipStream_t stream);
 hipError_t launch_wta_lrc(const uint16_t* agg, int width, int height, int ndisp,
                           int lr_tolerance, int median3x3, uint16_t* disp,
                           uint16_t* disp_right, uint16_t* work, hipStream_t stream);

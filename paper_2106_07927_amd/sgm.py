@@ -28,8 +28,8 @@ SGM_ERR_ALIGN = -3
 SGM_ERR_HIP = -4
 SGM_ERR_WORKSPACE = -5
 
-EXPORTS = ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_wta_lrc", "sgm_wta_lrc_work_elems",
-           "sgm_status_string", "sgm_last_hip_error", "sgm_abi_version")
+EXPORTS = ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_aggregate_work_bytes", "sgm_wta_lrc",
+           "sgm_wta_lrc_work_elems", "sgm_status_string", "sgm_last_hip_error", "sgm_abi_version")
 
 
 class SGMError(RuntimeError):
@@ -54,7 +54,9 @@ def load_library(path: str = LIB_PATH):
     P, I32 = ctypes.c_void_p, ctypes.c_int32
     lib.sgm_census.argtypes = [P, I32, I32, I32, I32, I32, P, P]
     lib.sgm_cost.argtypes = [P, P, I32, I32, I32, P, P]
-    lib.sgm_aggregate.argtypes = [P, I32, I32, I32, I32, I32, I32, P, P]
+    lib.sgm_aggregate.argtypes = [P, I32, I32, I32, I32, I32, I32, P, P, ctypes.c_size_t, P]
+    lib.sgm_aggregate_work_bytes.argtypes = [I32, I32, I32, I32, I32]
+    lib.sgm_aggregate_work_bytes.restype = ctypes.c_size_t
     lib.sgm_wta_lrc.argtypes = [P, I32, I32, I32, I32, I32, P, P, P, P]
     lib.sgm_wta_lrc_work_elems.argtypes = [I32, I32]
     lib.sgm_wta_lrc_work_elems.restype = ctypes.c_size_t
@@ -138,17 +140,27 @@ def sgm_cost(census_left: torch.Tensor, census_right: torch.Tensor, ndisp: int,
     return out
 
 
+def aggregate_work_bytes(width: int, height: int, ndisp: int, npaths: int, p2: int) -> int:
+    return int(load_library().sgm_aggregate_work_bytes(width, height, ndisp, npaths, p2))
+
+
 def sgm_aggregate(cost: torch.Tensor, npaths: int, p1: int, p2: int,
-                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """SGM path aggregation; returns uint16 [H][W][D]."""
+                  out: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """SGM path aggregation; returns uint16 [H][W][D].  `work` is a uint8
+    device scratch tensor of at least aggregate_work_bytes(...) bytes."""
     if cost.dtype != torch.uint8 or cost.dim() != 3:
         raise ValueError("cost must be a 3-D uint8 tensor")
     h, w, nd = cost.shape
     if out is None:
         out = _empty((h, w, nd), torch.uint16, cost.device)
     _expect(out, torch.uint16, (h, w, nd), "out")
+    if work is None:
+        work = _empty((max(1, aggregate_work_bytes(w, h, nd, npaths, p2)),), torch.uint8, cost.device)
+    if work.dtype != torch.uint8:
+        raise ValueError("work must be a uint8 tensor")
     _check(load_library().sgm_aggregate(_ptr(cost), w, h, nd, npaths, p1, p2, _ptr(out),
-                                        _stream(stream)))
+                                        _ptr(work), work.numel(), _stream(stream)))
     return out
 
 
@@ -204,6 +216,8 @@ class StereoSGM:
         self.census_right = _empty((height, width), torch.uint64, dev)
         self.cost = _empty((height, width, nd), torch.uint8, dev)
         self.agg = _empty((height, width, nd), torch.uint16, dev)
+        self.agg_work = _empty((max(1, aggregate_work_bytes(width, height, nd, params.npaths, params.p2)),),
+                               torch.uint8, dev)
         self.disp = _empty((height, width), torch.uint16, dev)
         self.disp_right = _empty((height, width), torch.uint16, dev)
         self.work = _empty((wta_lrc_work_elems(width, height),), torch.uint16, dev)
@@ -213,7 +227,7 @@ class StereoSGM:
         sgm_census(left, p.win_w, p.win_h, out=self.census_left, width=self.width, stream=stream)
         sgm_census(right, p.win_w, p.win_h, out=self.census_right, width=self.width, stream=stream)
         sgm_cost(self.census_left, self.census_right, p.ndisp, out=self.cost, stream=stream)
-        sgm_aggregate(self.cost, p.npaths, p.p1, p.p2, out=self.agg, stream=stream)
+        sgm_aggregate(self.cost, p.npaths, p.p1, p.p2, out=self.agg, work=self.agg_work, stream=stream)
         sgm_wta_lrc(self.agg, p.lr_tolerance, p.median3x3, out=self.disp,
                     out_right=self.disp_right, work=self.work, stream=stream)
         return self.disp

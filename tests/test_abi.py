@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings_and_version(lib):
-    assert lib.sgm_abi_version() == 1
+    assert lib.sgm_abi_version() == 2
     for code in (OK, ARG, UNSUP, ALIGN, HIP, WS):
         assert lib.sgm_status_string(code).decode().startswith("SGM_")
     assert lib.sgm_status_string(99) == b"unknown sgm status"
@@ -75,15 +75,25 @@ def test_cost_validation(lib):
 
 def test_aggregate_validation(lib):
     f = lib.sgm_aggregate
-    assert f(P(NULL), 8, 8, 16, 8, 10, 120, P(FAKE), P(NULL)) == ARG
-    assert f(P(FAKE), 8, 8, 16, 6, 10, 120, P(FAKE), P(NULL)) == ARG    # npaths
-    assert f(P(FAKE), 8, 8, 16, 8, 121, 120, P(FAKE), P(NULL)) == ARG   # p1 > p2
-    assert f(P(FAKE), 8, 8, 16, 8, -1, 120, P(FAKE), P(NULL)) == ARG
-    assert f(P(FAKE), 8, 8, 16, 8, 10, 7937, P(FAKE), P(NULL)) == ARG   # 8 * (255 + p2) > 65535
-    assert f(P(FAKE), 8, 8, 16, 4, 10, 16129, P(FAKE), P(NULL)) == ARG
-    assert f(P(FAKE), 8, 8, 300, 8, 10, 120, P(FAKE), P(NULL)) == ARG
-    assert f(P(FAKE + 8), 8, 8, 16, 8, 10, 120, P(FAKE), P(NULL)) == ALIGN
-    assert f(P(FAKE), 8, 8, 16, 8, 10, 120, P(FAKE + 2), P(NULL)) == ALIGN
+    big = 1 << 40
+    W = lambda v: ctypes.c_size_t(v)
+    assert f(P(NULL), 8, 8, 16, 8, 10, 120, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 16, 6, 10, 120, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG   # npaths
+    assert f(P(FAKE), 8, 8, 16, 8, 121, 120, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG  # p1 > p2
+    assert f(P(FAKE), 8, 8, 16, 8, -1, 120, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 16, 8, 10, 7937, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG  # 8 * (255 + p2) > 65535
+    assert f(P(FAKE), 8, 8, 16, 4, 10, 16129, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG
+    assert f(P(FAKE), 8, 8, 300, 8, 10, 120, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG
+    assert f(P(FAKE), 32768, 32768, 4, 8, 10, 120, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG  # volume
+    assert f(P(FAKE), 8, 8, 16, 8, 10, 120, P(FAKE), P(NULL), W(big), P(NULL)) == WS
+    need = lib.sgm_aggregate_work_bytes(8, 8, 16, 8, 120)
+    assert need == 8 * 1024                                    # 8 slices of 1024 uint8
+    assert lib.sgm_aggregate_work_bytes(8, 8, 16, 8, 256) == 8 * 1024 * 2
+    assert lib.sgm_aggregate_work_bytes(8, 8, 16, 8, 7937) == 0
+    assert f(P(FAKE), 8, 8, 16, 8, 10, 120, P(FAKE), P(FAKE), W(need - 1), P(NULL)) == WS
+    assert f(P(FAKE + 8), 8, 8, 16, 8, 10, 120, P(FAKE), P(FAKE), W(need), P(NULL)) == ALIGN
+    assert f(P(FAKE), 8, 8, 16, 8, 10, 120, P(FAKE + 2), P(FAKE), W(need), P(NULL)) == ALIGN
+    assert f(P(FAKE), 8, 8, 16, 8, 10, 120, P(FAKE), P(FAKE + 4), W(need), P(NULL)) == ALIGN
 
 
 def test_wta_lrc_validation(lib):
