@@ -13,9 +13,14 @@
 namespace sgm {
 namespace {
 
-constexpr int kPix = 64;
+constexpr int kPix = 128;
 constexpr int kMaxD = 256;
 
+// D a multiple of 4.  Thread (q, g) produces disparities 4q .. 4q+3 for the
+// PPG consecutive pixels of group g; the right descriptors it needs,
+// CR(x - d) for those pixels and disparities, are PPG + 3 consecutive LDS
+// entries, read once into registers and reused across the run.
+template <int PPG>
 __global__ __launch_bounds__(256) void cost_kernel_vec4(const uint64_t* __restrict__ cl,
                                                         const uint64_t* __restrict__ cr,
                                                         int width, int ndisp,
@@ -36,28 +41,35 @@ __global__ __launch_bounds__(256) void cost_kernel_vec4(const uint64_t* __restri
     __syncthreads();
 
     const int dwords = ndisp >> 2;                 // dwords per pixel
-    const int per_pass = blockDim.x / dwords;      // pixels per pass
     const int q = threadIdx.x % dwords;
-    const int p0 = threadIdx.x / dwords;
-    if (p0 >= per_pass) return;
+    const int g = threadIdx.x / dwords;
     const int d0 = q * 4;
+    const int p0 = g * PPG;
+    if (p0 >= npix) return;
+    // sr index of CR(x - d) for pixel p: p + ndisp - 1 - d
+    const int rb = p0 + ndisp - 1 - d0 - 3;
+    uint64_t r[PPG + 3];
+#pragma unroll
+    for (int k = 0; k < PPG + 3; ++k) r[k] = (rb + k < npix + ndisp - 1) ? sr[rb + k] : 0ull;
     uint32_t* out = reinterpret_cast<uint32_t*>(cost + ((size_t)y * width + x0) * ndisp);
-    for (int p = p0; p < npix; p += per_pass) {
-        const uint64_t l = sl[p];
-        const int x = x0 + p;
-        // sr index of the right pixel x - d is p + (ndisp - 1) - d
-        const int base = p + ndisp - 1 - d0;
-        uint32_t c0 = __popcll(l ^ sr[base]);
-        uint32_t c1 = __popcll(l ^ sr[base - 1]);
-        uint32_t c2 = __popcll(l ^ sr[base - 2]);
-        uint32_t c3 = __popcll(l ^ sr[base - 3]);
-        if (x < d0 + 3) {                           // some of d0..d0+3 exceed x
-            c0 = (x - d0 >= 0) ? c0 : 255u;
-            c1 = (x - d0 - 1 >= 0) ? c1 : 255u;
-            c2 = (x - d0 - 2 >= 0) ? c2 : 255u;
-            c3 = (x - d0 - 3 >= 0) ? c3 : 255u;
+#pragma unroll
+    for (int i = 0; i < PPG; ++i) {
+        const int p = p0 + i;
+        if (p < npix) {
+            const uint64_t l = sl[p];
+            uint32_t c0 = __popcll(l ^ r[i + 3]);
+            uint32_t c1 = __popcll(l ^ r[i + 2]);
+            uint32_t c2 = __popcll(l ^ r[i + 1]);
+            uint32_t c3 = __popcll(l ^ r[i]);
+            const int x = x0 + p;
+            if (x < d0 + 3) {                       // some of d0..d0+3 exceed x
+                c0 = (x - d0 >= 0) ? c0 : 255u;
+                c1 = (x - d0 - 1 >= 0) ? c1 : 255u;
+                c2 = (x - d0 - 2 >= 0) ? c2 : 255u;
+                c3 = (x - d0 - 3 >= 0) ? c3 : 255u;
+            }
+            out[p * dwords + q] = c0 | (c1 << 8) | (c2 << 16) | (c3 << 24);
         }
-        out[p * dwords + q] = c0 | (c1 << 8) | (c2 << 16) | (c3 << 24);
     }
 }
 
@@ -94,9 +106,17 @@ hipError_t launch_cost(const uint64_t* cl, const uint64_t* cr, int width, int he
                        int ndisp, uint8_t* cost, hipStream_t stream) {
     const dim3 grid((width + kPix - 1) / kPix, height);
     if ((ndisp & 3) == 0) {
+        // groups of PPG pixels; at most 256 threads cover all dwords of kPix pixels
         const int dwords = ndisp / 4;
-        const int threads = dwords * (dwords >= 256 ? 1 : 256 / dwords);
-        cost_kernel_vec4<<<grid, threads, 0, stream>>>(cl, cr, width, ndisp, cost);
+        const int need = (kPix * dwords + 255) / 256;             // pixels per group, at least
+        const int ppg = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : 32;
+        const int threads = dwords * ((kPix + ppg - 1) / ppg);
+        if (ppg == 1) cost_kernel_vec4<1><<<grid, threads, 0, stream>>>(cl, cr, width, ndisp, cost);
+        else if (ppg == 2) cost_kernel_vec4<2><<<grid, threads, 0, stream>>>(cl, cr, width, ndisp, cost);
+        else if (ppg == 4) cost_kernel_vec4<4><<<grid, threads, 0, stream>>>(cl, cr, width, ndisp, cost);
+        else if (ppg == 8) cost_kernel_vec4<8><<<grid, threads, 0, stream>>>(cl, cr, width, ndisp, cost);
+        else if (ppg == 16) cost_kernel_vec4<16><<<grid, threads, 0, stream>>>(cl, cr, width, ndisp, cost);
+        else cost_kernel_vec4<32><<<grid, threads, 0, stream>>>(cl, cr, width, ndisp, cost);
     } else {
         cost_kernel_bytes<<<grid, 256, 0, stream>>>(cl, cr, width, ndisp, cost);
     }

@@ -5,17 +5,20 @@
 //
 // Pass 1 (select_kernel): one wave walks a segment of one row, one pixel per
 // step, reading that pixel's S_bar vector once and coalesced (lane j holds
-// disparities j*EPL .. j*EPL+EPL-1).  Every value becomes a 32-bit key
-// (S_bar << 8) | d, so a plain minimum yields the smallest cost and, among
-// equal costs, the smallest d.
-//  * D^L(x): all-reduce of the keys over the wave (DPP + permlane swaps).
+// disparities j*EPL .. j*EPL+EPL-1); loads run a chunk of pixels ahead.
+// Every value becomes a 32-bit key (S_bar << 8) | d, so a plain minimum
+// yields the smallest cost and, among equal costs, the smallest d.
+//  * D^L(x): each lane parks the minimum of its own keys for the step in an
+//    LDS tile [step][lane]; every 64 steps lane i reduces row i, i.e. pixel i,
+//    so the cross-lane reduction costs one LDS write and read per step.
 //  * D^R(q) = min_d key(q + d, d): lane d keeps T_d, the running minimum for
 //    q = x - d over the disparities d' <= d seen so far; each step every lane
 //    takes its left neighbour's T (a one-lane shift) and folds in its own
 //    key.  The lane holding d = D-1 then holds the complete minimum for
-//    q = x - D + 1.  Partial minima left at a segment's end are merged with
-//    the next segment's through a 32-bit atomicMin on a key map, so S_bar is
-//    read exactly once, in order, with no strided gather.
+//    q = x - D + 1.  Those minima are gathered 64 at a time and merged with a
+//    coalesced 32-bit atomicMin into a key map, as are the partial minima
+//    left in the lanes at a segment's end, so S_bar is read exactly once,
+//    in order, with no strided gather.
 // Pass 2 (check_median_kernel): per 64x4 tile plus a one-pixel halo, applies
 // the LR check into LDS, then the median over the 3x3 window with 0xFFFF for
 // pixels outside the image and for invalid pixels.
@@ -29,70 +32,144 @@ constexpr uint16_t kInvalid = 0xFFFFu;
 constexpr int kSeg = 128;          // pixels per wave segment
 constexpr int kSegWaves = 4;
 
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-    v = group_min<16>(v);
-    auto s16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    v = min((uint32_t)s16[0], (uint32_t)s16[1]);
-    auto s32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return min((uint32_t)s32[0], (uint32_t)s32[1]);
-}
-
 __device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t edge) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xF, 0xF, false);
 }
 
+// Raw S_bar words of one lane for one pixel: EPL consecutive disparities as
+// uint16, unpacked only when used.
 template <int EPL>
+struct RawVals {
+    static constexpr int kWords = (EPL + 1) / 2;
+    uint32_t w[kWords];
+};
+
+template <int EPL, bool VEC>
+__device__ __forceinline__ RawVals<EPL> load_vals(const uint16_t* __restrict__ agg, size_t pix,
+                                                  int d0, int ndisp) {
+    RawVals<EPL> r;
+    const uint16_t* p = agg + pix * ndisp + (d0 < ndisp ? d0 : 0);
+    if constexpr (VEC && EPL == 1) {
+        r.w[0] = *p;
+    } else if constexpr (VEC && EPL == 2) {
+        r.w[0] = *reinterpret_cast<const uint32_t*>(p);
+    } else if constexpr (VEC && EPL == 4) {
+        const uint2 w = *reinterpret_cast<const uint2*>(p);
+        r.w[0] = w.x;
+        r.w[1] = w.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < RawVals<EPL>::kWords; ++i) r.w[i] = 0;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e)
+            if (d0 + e < ndisp) r.w[e >> 1] |= (uint32_t)p[e] << (16 * (e & 1));
+    }
+    return r;
+}
+
+template <int EPL>
+__device__ __forceinline__ uint32_t val(const RawVals<EPL>& r, int e) {
+    return (e & 1) ? (r.w[e >> 1] >> 16) : (r.w[e >> 1] & 0xFFFFu);
+}
+
+// T[e] for a wave-uniform e, without indexing a register array
+template <int EPL>
+__device__ __forceinline__ uint32_t pick(const uint32_t (&T)[EPL], int e) {
+    uint32_t r = T[0];
+#pragma unroll
+    for (int i = 1; i < EPL; ++i) r = (e == i) ? T[i] : r;
+    return r;
+}
+
+template <int EPL, bool VEC>
 __global__ __launch_bounds__(64 * kSegWaves) void select_kernel(const uint16_t* __restrict__ agg,
                                                                 int width, int ndisp,
                                                                 uint16_t* __restrict__ disp_left,
                                                                 uint32_t* __restrict__ right_keys) {
+    constexpr int K = 16;                      // pixels per load chunk
+    __shared__ uint32_t tile[kSegWaves][64][65];
     const int lane = threadIdx.x & 63;
-    const int seg = blockIdx.x * kSegWaves + (threadIdx.x >> 6);
+    const int wave = threadIdx.x >> 6;
+    const int seg = blockIdx.x * kSegWaves + wave;
     const int y = blockIdx.y;
     const int x0 = seg * kSeg;
     if (x0 >= width) return;                       // uniform per wave
     const int x1 = min(width, x0 + kSeg);
     const size_t row = (size_t)y * width;
+    const int d0 = lane * EPL;
     const int dlast_lane = (ndisp - 1) / EPL;
     const int dlast_e = (ndisp - 1) % EPL;
+    uint32_t (*tl)[65] = tile[wave];
 
     uint32_t T[EPL];
 #pragma unroll
     for (int e = 0; e < EPL; ++e) T[e] = kInf;
-    uint32_t dl_keep = 0;
+    uint32_t emit = kInf;                          // lane i: D^R key emitted at step base + i
 
-    for (int x = x0; x < x1; ++x) {
-        const uint16_t* px = agg + (row + x) * ndisp;
+    auto step = [&](const RawVals<EPL>& cv, int x) {
         uint32_t key[EPL];
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-            const int d = lane * EPL + e;
-            key[e] = d < ndisp ? (((uint32_t)px[d] << 8) | (uint32_t)d) : kInf;
-        }
-        // D^L
+        for (int e = 0; e < EPL; ++e)
+            key[e] = (d0 + e < ndisp) ? ((val<EPL>(cv, e) << 8) | (uint32_t)(d0 + e)) : kInf;
         uint32_t k = key[0];
 #pragma unroll
         for (int e = 1; e < EPL; ++e) k = min(k, key[e]);
-        k = wave_min(k);
         const int slot = (x - x0) & 63;
-        if (lane == slot) dl_keep = k & 0xFFu;
-        if (slot == 63 || x == x1 - 1) {
-            if (lane <= slot) disp_left[row + (x - slot) + lane] = (uint16_t)dl_keep;
-        }
+        tl[slot][lane] = k;
         // D^R chain: T_d <- min(T_{d-1}, key_d)
         const uint32_t carry = wave_shr1(T[EPL - 1], kInf);
 #pragma unroll
         for (int e = EPL - 1; e >= 1; --e) T[e] = min(T[e - 1], key[e]);
         T[0] = min(lane == 0 ? kInf : carry, key[0]);
-        if (lane == dlast_lane) {
-            const int q = x - (ndisp - 1);
-            if (q >= 0) atomicMin(&right_keys[row + q], T[dlast_e]);
+        const uint32_t done = __builtin_amdgcn_readlane(pick<EPL>(T, dlast_e), dlast_lane);
+        emit = (lane == slot) ? done : emit;
+        if (slot == 63 || x == x1 - 1) {
+            // D^L of the pixels base .. x: lane i reduces row i of the tile
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int base = x - slot;
+            if (lane <= slot) {
+                uint32_t best = tl[lane][0];
+#pragma unroll 8
+                for (int i = 1; i < 64; ++i) best = min(best, tl[lane][i]);
+                disp_left[row + base + lane] = (uint16_t)(best & 0xFFu);
+                const int q = base + lane - (ndisp - 1);
+                if (q >= 0) atomicMin(&right_keys[row + q], emit);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            emit = kInf;
+        }
+    };
+
+    int xl = x0;                                   // next pixel to load
+    RawVals<EPL> nxt[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        nxt[j] = load_vals<EPL, VEC>(agg, row + xl, d0, ndisp);
+        xl = min(xl + 1, x1 - 1);
+    }
+    for (int xc = x0; xc < x1; xc += K) {
+        RawVals<EPL> cur[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) cur[j] = nxt[j];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            nxt[j] = load_vals<EPL, VEC>(agg, row + xl, d0, ndisp);
+            xl = min(xl + 1, x1 - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int x = xc + j;
+            if (x < x1) step(cur[j], x);          // uniform
         }
     }
     // partial minima still travelling through the lanes
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-        const int d = lane * EPL + e;
+        const int d = d0 + e;
         const int q = x1 - 1 - d;
         if (d < ndisp - 1 && q >= 0 && T[e] != kInf) atomicMin(&right_keys[row + q], T[e]);
     }
@@ -182,9 +259,15 @@ hipError_t launch_wta_lrc(const uint16_t* agg, int width, int height, int ndisp,
     }
     const int segs = (width + kSeg - 1) / kSeg;
     const dim3 g1((segs + kSegWaves - 1) / kSegWaves, height);
-    if (ndisp <= 64) select_kernel<1><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
-    else if (ndisp <= 128) select_kernel<2><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
-    else select_kernel<4><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
+    if (ndisp <= 64) {
+        select_kernel<1, true><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
+    } else if (ndisp <= 128) {
+        if (ndisp % 2 == 0) select_kernel<2, true><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
+        else select_kernel<2, false><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
+    } else {
+        if (ndisp % 4 == 0) select_kernel<4, true><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
+        else select_kernel<4, false><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 g2((width + kTW - 1) / kTW, (height + kTH - 1) / kTH);
