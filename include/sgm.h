@@ -139,6 +139,66 @@ int32_t sgm_wta_lrc(const uint16_t* agg, int32_t width, int32_t height,
 /* Number of uint16 elements sgm_wta_lrc needs in `work` (0 on bad sizes). */
 size_t sgm_wta_lrc_work_elems(int32_t width, int32_t height);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many rectified pairs, each with its own size and disparity
+ * range, run as one hipGraph launch.  Each pair's outputs are bit-identical
+ * to the four single-frame calls above with the same parameters.
+ * ------------------------------------------------------------------------- */
+
+/* Parameters shared by every pair of a batch (meanings as above). */
+typedef struct {
+    int32_t win_w, win_h;        /* census window: (5,5) or (9,7)               */
+    int32_t npaths;              /* 4 or 8                                      */
+    int32_t p1, p2;              /* 0 <= p1 <= p2, npaths * (255 + p2) <= 65535 */
+    int32_t lr_tolerance;        /* < 0: no LR check                            */
+    int32_t median3x3;           /* 0 or 1                                      */
+} sgm_params;
+
+/* One pair of a batch.  Device pointers owned by the caller; they must stay
+ * valid, and their shapes unchanged, for the life of the plan. */
+typedef struct {
+    const uint8_t* left;         /* uint8 [height][pitch_bytes]                 */
+    const uint8_t* right;        /* uint8 [height][pitch_bytes]                 */
+    int32_t width, height, pitch_bytes;
+    int32_t ndisp;               /* 1 .. 256                                    */
+    uint16_t* disp_out;          /* uint16 [height][width], 4-byte aligned      */
+    uint16_t* disp_right_out;    /* uint16 [height][width] (D^R) or NULL        */
+} sgm_pair;
+
+typedef struct sgm_plan sgm_plan;
+
+/* Device workspace a plan needs for these pairs (0 on invalid arguments):
+ * every pair's intermediates plus the plan's work-list tables. */
+size_t sgm_batch_workspace_bytes(const sgm_pair* pairs, int32_t n,
+                                 const sgm_params* params);
+
+/*
+ * Lays the intermediates out in `workspace` (256-byte aligned, at least
+ * sgm_batch_workspace_bytes bytes, owned by the caller and kept alive with
+ * the plan), copies the work lists to the device (a synchronous copy), and
+ * captures the whole batch into a hipGraph on a stream of its own.
+ * tune_table: NULL, or a JSON object mapping "WxHxD" to the path-kernel
+ * lane-layout variant to use for pairs of that shape (written by the
+ * project's tuner; unknown shapes use variant 0).  Variants never change
+ * results.
+ * Errors: SGM_ERR_ARG, SGM_ERR_WORKSPACE, SGM_ERR_ALIGN, SGM_ERR_HIP.
+ */
+int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n,
+                              const sgm_params* params, void* workspace,
+                              size_t workspace_bytes, const char* tune_table,
+                              sgm_plan** plan_out);
+
+/* Enqueues the captured batch on `stream` (one hipGraphLaunch).  Replays of
+ * one plan must not overlap. */
+int32_t sgm_batch_run(sgm_plan* plan, void* stream);
+
+/* Number of pairs of a plan (0 for NULL). */
+int32_t sgm_batch_frames(const sgm_plan* plan);
+
+/* Releases the graph and the plan's stream; the workspace stays the
+ * caller's.  Accepts NULL. */
+void sgm_batch_plan_destroy(sgm_plan* plan);
+
 /* Human-readable name of a status code. */
 const char* sgm_status_string(int32_t status);
 

@@ -21,7 +21,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsgm.so")
 
 HIP_SOURCES = ["census.hip", "cost.hip", "aggregate.hip", "wta_lrc.hip"]
-CPP_SOURCES = ["sgm_capi.cpp"]
+CPP_SOURCES = ["sgm_capi.cpp", "batch.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I", INCLUDE, "-I", CSRC]

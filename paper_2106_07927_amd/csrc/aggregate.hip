@@ -50,13 +50,45 @@ struct DirTask {
     int dx, dy;      // step r: the predecessor of p is p - r
     int nlines;      // independent lines of this direction
     int nsteps;      // pixels per line
-    int block0;      // first block of this direction in the grid
 };
 
-struct DirTable {
-    DirTask t[8];
-    int ndir;
-};
+// The path set in launch order: the long horizontal chains first, so their
+// blocks are dispatched first.  4 paths: LR, RL, TB, BT; 8 adds the diagonals.
+__host__ __device__ inline void path_dir(int i, int* dx, int* dy) {
+    constexpr int kDirs[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1},
+                                 {1, 1}, {-1, 1}, {1, -1}, {-1, -1}};
+    *dx = kDirs[i][0];
+    *dy = kDirs[i][1];
+}
+
+// Blocks of direction i: lines / (lines per block).
+__host__ __device__ inline int dir_blocks(int i, int width, int height, int lpl_h, int lpl_o) {
+    int dx, dy;
+    path_dir(i, &dx, &dy);
+    const bool horiz = dy == 0;
+    const int nlines = horiz ? height : width;
+    const int lines_per_block = kWaves * (64 / (horiz ? lpl_h : lpl_o));
+    return (nlines + lines_per_block - 1) / lines_per_block;
+}
+
+// Direction and first block of block lb of a frame.
+__device__ __forceinline__ DirTask find_dir(int lb, int width, int height, int npaths, int lpl_h,
+                                            int lpl_o, int* block0, int* index) {
+    int start = 0, i = 0;
+    for (; i < npaths - 1; ++i) {
+        const int nb = dir_blocks(i, width, height, lpl_h, lpl_o);
+        if (lb < start + nb) break;
+        start += nb;
+    }
+    DirTask t;
+    path_dir(i, &t.dx, &t.dy);
+    const bool horiz = t.dy == 0;
+    t.nlines = horiz ? height : width;
+    t.nsteps = horiz ? width : height;
+    *block0 = start;
+    *index = i;
+    return t;
+}
 
 // ---- cross-lane helpers for lines of up to 64 lanes -----------------------
 template <int GROUP>
@@ -294,57 +326,69 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
     }
 }
 
+// Block lb of the path pass of one frame.
 template <int NH, int LH, int NO, int LO, bool ALH, bool PDH, bool ALO, bool PDO, bool U8>
-__global__ __launch_bounds__(kThreads) void paths_kernel(const uint8_t* __restrict__ cost,
-                                                         uint8_t* __restrict__ slices,
-                                                         size_t slice_elems, int width, int height,
-                                                         int ndisp, uint32_t p1x2, uint32_t p2x2,
-                                                         DirTable tab) {
+__device__ __forceinline__ void paths_block(const Frame& f, int lb) {
     // steps per chunk: enough to cover a memory round trip, few enough to
     // keep two chunks of cost bytes in registers
     constexpr int KH = NH == 1 ? 32 : 16;
     constexpr int KO = NO <= 4 ? 16 : 8;
-    int di = 0;
-#pragma unroll
-    for (int i = 1; i < 8; ++i)
-        if (i < tab.ndir && (int)blockIdx.x >= tab.t[i].block0) di = i;
-    const DirTask task = tab.t[di];
-    const int wave_in_dir = ((int)blockIdx.x - task.block0) * kWaves + (int)(threadIdx.x >> 6);
-    void* slice = slices + (size_t)di * slice_elems * (U8 ? 1 : 2);
+    int block0, di;
+    const DirTask task = find_dir(lb, f.width, f.height, f.npaths, LH, LO, &block0, &di);
+    const int wave_in_dir = (lb - block0) * kWaves + (int)(threadIdx.x >> 6);
+    void* slice = f.slices + (size_t)di * f.slice_stride * (U8 ? 1 : 2);
+    const uint32_t p1x2 = pk_splat((uint32_t)f.p1);
+    const uint32_t p2x2 = pk_splat((uint32_t)f.p2);
     if (task.dy == 0) {
         __builtin_amdgcn_s_setprio(2);
-        run_lines<kHorizontal, NH, LH, KH, ALH, PDH, U8>(cost, slice, width, height, ndisp, p1x2, p2x2,
-                                                         task, wave_in_dir);
+        run_lines<kHorizontal, NH, LH, KH, ALH, PDH, U8>(f.cost, slice, f.width, f.height, f.ndisp,
+                                                         p1x2, p2x2, task, wave_in_dir);
+        __builtin_amdgcn_s_setprio(0);
     } else if (task.dx == 0) {
-        run_lines<kVertical, NO, LO, KO, ALO, PDO, U8>(cost, slice, width, height, ndisp, p1x2, p2x2,
-                                                       task, wave_in_dir);
+        run_lines<kVertical, NO, LO, KO, ALO, PDO, U8>(f.cost, slice, f.width, f.height, f.ndisp,
+                                                       p1x2, p2x2, task, wave_in_dir);
     } else {
-        run_lines<kDiagonal, NO, LO, KO, ALO, PDO, U8>(cost, slice, width, height, ndisp, p1x2, p2x2,
-                                                       task, wave_in_dir);
+        run_lines<kDiagonal, NO, LO, KO, ALO, PDO, U8>(f.cost, slice, f.width, f.height, f.ndisp,
+                                                       p1x2, p2x2, task, wave_in_dir);
     }
 }
 
-// S_bar = R * C + sum_r A_r over uint8 penalty slices (slice r starts at
-// r * stride), 16 elements per thread and iteration.  Bytes are split into
-// even/odd 16-bit lanes so that plain 32-bit adds accumulate two sums per
-// register without carries.
-__global__ __launch_bounds__(256) void merge_u8_kernel(const uint8_t* __restrict__ cost,
-                                                       const uint8_t* __restrict__ slices,
-                                                       size_t n, size_t stride_elems, int npaths,
-                                                       uint16_t* __restrict__ agg) {
-    const size_t n16 = n / 16;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+template <int NH, int LH, int NO, int LO, bool ALH, bool PDH, bool ALO, bool PDO, bool U8>
+__global__ __launch_bounds__(kThreads) void paths_kernel(Frame f) {
+    paths_block<NH, LH, NO, LO, ALH, PDH, ALO, PDO, U8>(f, blockIdx.x);
+}
+
+template <int NH, int LH, int NO, int LO, bool ALH, bool PDH, bool ALO, bool PDO, bool U8>
+__global__ __launch_bounds__(kThreads) void paths_batch_kernel(WorkList wl) {
+    for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
+        const int fi = find_frame(wl, b);
+        paths_block<NH, LH, NO, LO, ALH, PDH, ALO, PDO, U8>(wl.frames[fi], b - wl.starts[fi]);
+    }
+}
+
+// S_bar = R * C + sum_r A_r over uint8 penalty slices, for the kMergeChunk
+// elements of block lb; each thread sums 16 consecutive elements.  Bytes are
+// split into even/odd 16-bit lanes so that plain 32-bit adds accumulate two
+// sums per register without carries.
+__device__ __forceinline__ void merge_u8_block(const Frame& f, int lb) {
+    const size_t n = (size_t)f.width * f.height * f.ndisp;
+    const size_t e0 = (size_t)lb * kMergeChunk + (size_t)threadIdx.x * 16;
+    const uint8_t* cost = f.cost;
+    const uint8_t* slices = f.slices;
+    uint16_t* agg = f.agg;
+    const uint32_t npaths = (uint32_t)f.npaths;
+    if (e0 + 16 <= n) {
+        const size_t i = e0 / 16;
         const uint4 c = reinterpret_cast<const uint4*>(cost)[i];
-        uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+        const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
         uint32_t ev[4], od[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            ev[q] = (cw[q] & 0x00FF00FFu) * (uint32_t)npaths;
-            od[q] = ((cw[q] >> 8) & 0x00FF00FFu) * (uint32_t)npaths;
+            ev[q] = (cw[q] & 0x00FF00FFu) * npaths;
+            od[q] = ((cw[q] >> 8) & 0x00FF00FFu) * npaths;
         }
-        for (int r = 0; r < npaths; ++r) {
-            const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * stride_elems)[i];
+        for (uint32_t r = 0; r < npaths; ++r) {
+            const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * f.slice_stride)[i];
             const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -364,92 +408,145 @@ __global__ __launch_bounds__(256) void merge_u8_kernel(const uint8_t* __restrict
         hi.w = __builtin_amdgcn_perm(od[3], ev[3], 0x07060302u);
         reinterpret_cast<uint4*>(agg)[2 * i] = lo;
         reinterpret_cast<uint4*>(agg)[2 * i + 1] = hi;
-    }
-    // tail
-    if (blockIdx.x == 0) {
-        for (size_t e = n16 * 16 + threadIdx.x; e < n; e += blockDim.x) {
-            uint32_t s = (uint32_t)cost[e] * (uint32_t)npaths;
-            for (int r = 0; r < npaths; ++r) s += slices[(size_t)r * stride_elems + e];
+    } else {
+        for (size_t e = e0; e < n && e < e0 + 16; ++e) {
+            uint32_t s = (uint32_t)cost[e] * npaths;
+            for (uint32_t r = 0; r < npaths; ++r) s += slices[(size_t)r * f.slice_stride + e];
             agg[e] = (uint16_t)s;
         }
     }
 }
 
-// S_bar = sum_r L_r over uint16 path slices.
-__global__ __launch_bounds__(256) void merge_u16_kernel(const uint16_t* __restrict__ slices,
-                                                        size_t n, size_t stride_elems, int npaths,
-                                                        uint16_t* __restrict__ agg) {
-    const size_t n8 = n / 8;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) {
-        uint4 s = reinterpret_cast<const uint4*>(slices)[i];
-        for (int r = 1; r < npaths; ++r) {
-            const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * stride_elems)[i];
-            s.x = pk_add(s.x, a.x);
-            s.y = pk_add(s.y, a.y);
-            s.z = pk_add(s.z, a.z);
-            s.w = pk_add(s.w, a.w);
+// S_bar = sum_r L_r over uint16 path slices, 16 elements per thread.
+__device__ __forceinline__ void merge_u16_block(const Frame& f, int lb) {
+    const size_t n = (size_t)f.width * f.height * f.ndisp;
+    const size_t e0 = (size_t)lb * kMergeChunk + (size_t)threadIdx.x * 16;
+    const uint16_t* slices = reinterpret_cast<const uint16_t*>(f.slices);
+    uint16_t* agg = f.agg;
+    if (e0 + 16 <= n) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t i = e0 / 8 + h;
+            uint4 s = reinterpret_cast<const uint4*>(slices)[i];
+            for (int r = 1; r < f.npaths; ++r) {
+                const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * f.slice_stride)[i];
+                s.x = pk_add(s.x, a.x);
+                s.y = pk_add(s.y, a.y);
+                s.z = pk_add(s.z, a.z);
+                s.w = pk_add(s.w, a.w);
+            }
+            reinterpret_cast<uint4*>(agg)[i] = s;
         }
-        reinterpret_cast<uint4*>(agg)[i] = s;
-    }
-    if (blockIdx.x == 0) {
-        for (size_t e = n8 * 8 + threadIdx.x; e < n; e += blockDim.x) {
+    } else {
+        for (size_t e = e0; e < n && e < e0 + 16; ++e) {
             uint32_t s = 0;
-            for (int r = 0; r < npaths; ++r) s += slices[(size_t)r * stride_elems + e];
+            for (int r = 0; r < f.npaths; ++r) s += slices[(size_t)r * f.slice_stride + e];
             agg[e] = (uint16_t)s;
         }
     }
 }
 
-// Lane layout per disparity range: (NREG, LPL) with LPL * 2 * NREG >= D.
-struct Layout {
-    int nreg, lpl;
-};
-
-Layout layout_other(int ndisp) {
-    if (ndisp <= 2) return {1, 1};
-    if (ndisp <= 4) return {2, 1};
-    if (ndisp <= 8) return {4, 1};
-    if (ndisp <= 16) return {4, 2};
-    if (ndisp <= 32) return {4, 4};
-    if (ndisp <= 64) return {4, 8};
-    if (ndisp <= 128) return {4, 16};
-    return {8, 16};
+template <bool U8>
+__global__ __launch_bounds__(256) void merge_kernel(Frame f) {
+    if constexpr (U8) merge_u8_block(f, blockIdx.x);
+    else merge_u16_block(f, blockIdx.x);
 }
 
-Layout layout_horizontal(int ndisp) {
-    if (ndisp <= 2) return {1, 1};
-    if (ndisp <= 4) return {1, 2};
-    if (ndisp <= 8) return {1, 4};
-    if (ndisp <= 16) return {1, 8};
-    if (ndisp <= 32) return {1, 16};
-    if (ndisp <= 64) return {1, 32};
-    if (ndisp <= 128) return {1, 64};
-    return {2, 64};
+template <bool U8>
+__global__ __launch_bounds__(256) void merge_batch_kernel(WorkList wl) {
+    for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
+        const int fi = find_frame(wl, b);
+        if constexpr (U8) merge_u8_block(wl.frames[fi], b - wl.starts[fi]);
+        else merge_u16_block(wl.frames[fi], b - wl.starts[fi]);
+    }
 }
 
-template <int NH, int LH, int NO, int LO, bool U8>
-hipError_t launch_paths(const uint8_t* cost, uint8_t* slices, size_t n, int width, int height,
-                        int ndisp, uint32_t p1x2, uint32_t p2x2, const DirTable& tab, int nblocks,
-                        hipStream_t stream) {
+// Path-kernel launch for one lane layout; `batch` selects the persistent
+// work-list form.
+template <int NH, int LH, int NO, int LO>
+hipError_t launch_paths_layout(const Frame* one, const WorkList* wl, int ndisp, bool u8,
+                               int nblocks, hipStream_t stream) {
     const bool alh = ndisp % (2 * NH) == 0;
     const bool alo = ndisp % (2 * NO) == 0;
     const bool pdh = LH * 2 * NH > ndisp;
     const bool pdo = LO * 2 * NO > ndisp;
-#define SGM_PATHS(A, B, C, D)                                                                     \
-    paths_kernel<NH, LH, NO, LO, A, B, C, D, U8>                                                  \
-        <<<nblocks, kThreads, 0, stream>>>(cost, slices, n, width, height, ndisp, p1x2, p2x2, tab)
+    const int grid = one ? nblocks : persistent_grid(nblocks);
+#define SGM_PATHS(A, B, C, D, U)                                                                   \
+    do {                                                                                           \
+        if (one) paths_kernel<NH, LH, NO, LO, A, B, C, D, U><<<grid, kThreads, 0, stream>>>(*one); \
+        else paths_batch_kernel<NH, LH, NO, LO, A, B, C, D, U><<<grid, kThreads, 0, stream>>>(*wl); \
+    } while (0)
     if (alh && alo) {
-        if (!pdh && !pdo) SGM_PATHS(true, false, true, false);
-        else SGM_PATHS(true, true, true, true);
+        if (!pdh && !pdo) {
+            if (u8) SGM_PATHS(true, false, true, false, true);
+            else SGM_PATHS(true, false, true, false, false);
+        } else {
+            if (u8) SGM_PATHS(true, true, true, true, true);
+            else SGM_PATHS(true, true, true, true, false);
+        }
     } else {
-        SGM_PATHS(false, true, false, true);
+        if (u8) SGM_PATHS(false, true, false, true, true);
+        else SGM_PATHS(false, true, false, true, false);
     }
 #undef SGM_PATHS
     return hipGetLastError();
 }
 
+hipError_t launch_paths_any(const Frame* one, const WorkList* wl, int ndisp, int variant, bool u8,
+                            int nblocks, hipStream_t stream) {
+    const PathLayout l = path_layout(ndisp, variant);
+#define SGM_CASE(NH, LH, NO, LO)                                                          \
+    if (l.nreg_h == NH && l.lpl_h == LH && l.nreg_o == NO && l.lpl_o == LO)              \
+        return launch_paths_layout<NH, LH, NO, LO>(one, wl, ndisp, u8, nblocks, stream);
+    SGM_CASE(1, 1, 1, 1)
+    SGM_CASE(1, 2, 2, 1)
+    SGM_CASE(1, 4, 4, 1)
+    SGM_CASE(1, 8, 4, 2)
+    SGM_CASE(1, 16, 4, 4)
+    SGM_CASE(1, 32, 4, 8)
+    SGM_CASE(2, 16, 4, 8)
+    SGM_CASE(1, 64, 4, 16)
+    SGM_CASE(2, 32, 4, 16)
+    SGM_CASE(1, 64, 8, 8)
+    SGM_CASE(2, 64, 8, 16)
+    SGM_CASE(4, 32, 8, 16)
+#undef SGM_CASE
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+// Lane layouts per disparity range.  Variant 0 is the default; the others
+// trade the horizontal chains' per-step latency (more lanes per line) against
+// total VALU work (more disparities per lane).  All give identical results.
+int path_variants(int ndisp) {
+    if (ndisp <= 32) return 1;
+    if (ndisp <= 64) return 2;
+    if (ndisp <= 128) return 3;
+    return 2;
+}
+
+PathLayout path_layout(int ndisp, int variant) {
+    if (ndisp <= 2) return {1, 1, 1, 1};
+    if (ndisp <= 4) return {1, 2, 2, 1};
+    if (ndisp <= 8) return {1, 4, 4, 1};
+    if (ndisp <= 16) return {1, 8, 4, 2};
+    if (ndisp <= 32) return {1, 16, 4, 4};
+    if (ndisp <= 64) return variant == 1 ? PathLayout{2, 16, 4, 8} : PathLayout{1, 32, 4, 8};
+    if (ndisp <= 128) {
+        if (variant == 1) return {2, 32, 4, 16};
+        if (variant == 2) return {1, 64, 8, 8};
+        return {1, 64, 4, 16};
+    }
+    return variant == 1 ? PathLayout{4, 32, 8, 16} : PathLayout{2, 64, 8, 16};
+}
+
+int path_blocks(int width, int height, int ndisp, int npaths, int variant) {
+    const PathLayout l = path_layout(ndisp, variant);
+    int nb = 0;
+    for (int i = 0; i < npaths; ++i) nb += dir_blocks(i, width, height, l.lpl_h, l.lpl_o);
+    return nb;
+}
 
 // Slices start on 256-element boundaries so every vector access is aligned.
 size_t aggregate_slice_elems(int width, int height, int ndisp) {
@@ -461,56 +558,29 @@ size_t aggregate_work_bytes(int width, int height, int ndisp, int npaths, int p2
     return (size_t)npaths * aggregate_slice_elems(width, height, ndisp) * (p2 <= 255 ? 1 : 2);
 }
 
-hipError_t launch_aggregate(const uint8_t* cost, int width, int height, int ndisp, int npaths,
-                            int p1, int p2, uint16_t* agg, void* work, hipStream_t stream) {
-    static const int kDirs[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1},
-                                    {1, 1}, {-1, 1}, {1, -1}, {-1, -1}};
-    const Layout lh = layout_horizontal(ndisp);
-    const Layout lo = layout_other(ndisp);
-    // horizontal directions first: their blocks are dispatched first
-    DirTable tab{};
-    int nblocks = 0;
-    tab.ndir = npaths;
-    for (int i = 0; i < npaths; ++i) {
-        DirTask& t = tab.t[i];
-        t.dx = kDirs[i][0];
-        t.dy = kDirs[i][1];
-        const bool horiz = t.dy == 0;
-        t.nlines = horiz ? height : width;
-        t.nsteps = horiz ? width : height;
-        const int lpl = horiz ? lh.lpl : lo.lpl;
-        const int lines_per_block = kWaves * (64 / lpl);
-        t.block0 = nblocks;
-        nblocks += (t.nlines + lines_per_block - 1) / lines_per_block;
-    }
-    const uint32_t p1x2 = pk_splat((uint32_t)p1);
-    const uint32_t p2x2 = pk_splat((uint32_t)p2);
-    const size_t n = (size_t)width * height * ndisp;
-    const size_t stride = aggregate_slice_elems(width, height, ndisp);
-    const bool u8 = p2 <= 255;
-    uint8_t* slices = static_cast<uint8_t*>(work);
-
-    hipError_t e = hipErrorInvalidValue;
-#define SGM_AGG_CASE(NH, LH, NO, LO)                                                             \
-    if (lh.nreg == NH && lh.lpl == LH && lo.nreg == NO && lo.lpl == LO)                         \
-        e = u8 ? launch_paths<NH, LH, NO, LO, true>(cost, slices, stride, width, height, ndisp,   \
-                                                    p1x2, p2x2, tab, nblocks, stream)             \
-               : launch_paths<NH, LH, NO, LO, false>(cost, slices, stride, width, height, ndisp,  \
-                                                     p1x2, p2x2, tab, nblocks, stream);
-    SGM_AGG_CASE(1, 1, 1, 1)
-    SGM_AGG_CASE(1, 2, 2, 1)
-    SGM_AGG_CASE(1, 4, 4, 1)
-    SGM_AGG_CASE(1, 8, 4, 2)
-    SGM_AGG_CASE(1, 16, 4, 4)
-    SGM_AGG_CASE(1, 32, 4, 8)
-    SGM_AGG_CASE(1, 64, 4, 16)
-    SGM_AGG_CASE(2, 64, 8, 16)
-#undef SGM_AGG_CASE
+hipError_t launch_aggregate(const Frame& f, hipStream_t stream) {
+    const int variant = (f.variant >= 0 && f.variant < path_variants(f.ndisp)) ? f.variant : 0;
+    const bool u8 = f.p2 <= 255;
+    const int nb = path_blocks(f.width, f.height, f.ndisp, f.npaths, variant);
+    hipError_t e = launch_paths_any(&f, nullptr, f.ndisp, variant, u8, nb, stream);
     if (e != hipSuccess) return e;
+    const int mb = merge_blocks((size_t)f.width * f.height * f.ndisp);
+    if (u8) merge_kernel<true><<<mb, 256, 0, stream>>>(f);
+    else merge_kernel<false><<<mb, 256, 0, stream>>>(f);
+    return hipGetLastError();
+}
 
-    const int blocks = (int)std::min<size_t>((n / 16 + 255) / 256 + 1, 8192);
-    if (u8) merge_u8_kernel<<<blocks, 256, 0, stream>>>(cost, slices, n, stride, npaths, agg);
-    else merge_u16_kernel<<<blocks, 256, 0, stream>>>(reinterpret_cast<const uint16_t*>(slices), n, stride, npaths, agg);
+hipError_t launch_paths_batch(const WorkList& wl, int ndisp, int npaths, int p2, int variant,
+                              hipStream_t stream) {
+    (void)npaths;
+    if (variant < 0 || variant >= path_variants(ndisp)) variant = 0;
+    return launch_paths_any(nullptr, &wl, ndisp, variant, p2 <= 255, wl.total, stream);
+}
+
+hipError_t launch_merge_batch(const WorkList& wl, bool u8, hipStream_t stream) {
+    const int grid = persistent_grid(wl.total);
+    if (u8) merge_batch_kernel<true><<<grid, 256, 0, stream>>>(wl);
+    else merge_batch_kernel<false><<<grid, 256, 0, stream>>>(wl);
     return hipGetLastError();
 }
 

@@ -1,0 +1,305 @@
+// batch.cpp -- many stereo pairs of uneven size and disparity range in one
+// hipGraph launch (the batched form of the path).
+//
+// Plan creation lays every frame's intermediates out in the caller's
+// workspace, groups the frames by what the kernels are compiled for
+// (disparity range, and for the path pass the lane-layout variant chosen by
+// the tuning table), writes one device work list per stage and group, and
+// captures the whole sequence into a hipGraph:
+//     census (all frames, both images) -> cost (per D) -> paths (per D and
+//     variant) -> merge (all) -> D^R key fill (all) -> select (per D) ->
+//     LR check + median (all)
+// Every stage is one persistent launch that walks its work list of
+// (frame, block) items; the blocks of a frame are exactly those of the
+// single-frame call, so each frame's results are bit-identical to it.
+// Running the plan is one hipGraphLaunch.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sgm.h"
+#include "sgm_internal.h"
+
+struct sgm_plan {
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t nframes = 0;
+};
+
+namespace sgm {
+namespace {
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Bytes of one frame's intermediates, in workspace order.
+struct FrameLayout {
+    size_t census, cost, slices, agg, keys, dl, total;
+};
+
+FrameLayout frame_layout(int w, int h, int nd, int npaths, int p2) {
+    const size_t n = (size_t)w * h;
+    FrameLayout l{};
+    l.census = align256(8 * n);
+    l.cost = align256(n * nd);
+    l.slices = align256(aggregate_work_bytes(w, h, nd, npaths, p2));
+    l.agg = align256(2 * n * nd);
+    l.keys = align256(4 * n);
+    l.dl = align256(2 * n);
+    l.total = 2 * l.census + l.cost + l.slices + l.agg + l.keys + l.dl;
+    return l;
+}
+
+// Looks up "WxHxD": variant in a flat JSON object; -1 when absent.
+int tuned_variant(const char* table, int w, int h, int nd) {
+    if (!table) return -1;
+    char key[64];
+    snprintf(key, sizeof(key), "\"%dx%dx%d\"", w, h, nd);
+    const char* p = strstr(table, key);
+    if (!p) return -1;
+    p = strchr(p + strlen(key), ':');
+    if (!p) return -1;
+    return (int)strtol(p + 1, nullptr, 10);
+}
+
+enum Stage { kCensus, kCost, kPaths, kMerge, kFill, kSelect, kMedian, kStages };
+
+int stage_blocks(Stage st, const Frame& f) {
+    const size_t n = (size_t)f.width * f.height;
+    switch (st) {
+        case kCensus: return 2 * census_blocks(f.width, f.height);
+        case kCost: return cost_blocks_x(f.width) * f.height;
+        case kPaths: return path_blocks(f.width, f.height, f.ndisp, f.npaths, f.variant);
+        case kMerge: return merge_blocks(n * f.ndisp);
+        case kFill: return fill_blocks(n);
+        case kSelect: return select_blocks_x(f.width) * f.height;
+        case kMedian: return median_blocks(f.width, f.height);
+        default: return 0;
+    }
+}
+
+// One launch: a stage over a group of frames (indices into the frame table).
+struct Launch {
+    Stage stage;
+    int ndisp, variant;
+    std::vector<int> frames;
+    size_t frames_off = 0, starts_off = 0;   // workspace offsets of its tables
+    WorkList wl{};
+};
+
+}  // namespace
+}  // namespace sgm
+
+using namespace sgm;
+
+namespace {
+
+bool valid_params(const sgm_params* p) {
+    if (!p) return false;
+    if (!((p->win_w == 5 && p->win_h == 5) || (p->win_w == 9 && p->win_h == 7))) return false;
+    if (p->npaths != 4 && p->npaths != 8) return false;
+    if (p->p1 < 0 || p->p2 < p->p1) return false;
+    if ((int64_t)p->npaths * (255 + (int64_t)p->p2) > 65535) return false;
+    return p->median3x3 == 0 || p->median3x3 == 1;
+}
+
+bool valid_pair(const sgm_pair& q) {
+    if (!q.left || !q.right || !q.disp_out) return false;
+    if (q.width < 1 || q.height < 1 || q.width > SGM_MAX_SIDE || q.height > SGM_MAX_SIDE) return false;
+    if (q.pitch_bytes < q.width || q.ndisp < 1 || q.ndisp > SGM_MAX_NDISP) return false;
+    if ((int64_t)q.width * q.height * q.ndisp > (int64_t)SGM_MAX_VOLUME) return false;
+    if ((reinterpret_cast<uintptr_t>(q.disp_out) & 3) != 0) return false;
+    if (q.disp_right_out && (reinterpret_cast<uintptr_t>(q.disp_right_out) & 3) != 0) return false;
+    return true;
+}
+
+// Builds the frame table and the launch list; returns the workspace bytes.
+size_t build_layout(const sgm_pair* pairs, int32_t n, const sgm_params* p, const char* tune_table,
+                    std::vector<Frame>* frames, std::vector<Launch>* launches, size_t* tables_off) {
+    frames->clear();
+    launches->clear();
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        const sgm_pair& q = pairs[i];
+        Frame f{};
+        f.width = q.width;
+        f.height = q.height;
+        f.ndisp = q.ndisp;
+        f.pitch = q.pitch_bytes;
+        f.win_w = p->win_w;
+        f.win_h = p->win_h;
+        f.npaths = p->npaths;
+        f.p1 = p->p1;
+        f.p2 = p->p2;
+        f.lr_tolerance = p->lr_tolerance;
+        f.median3x3 = p->median3x3;
+        const int tv = tuned_variant(tune_table, q.width, q.height, q.ndisp);
+        f.variant = (tv >= 0 && tv < path_variants(q.ndisp)) ? tv : 0;
+        f.left = q.left;
+        f.right = q.right;
+        f.disp = q.disp_out;
+        f.disp_right = q.disp_right_out;
+        f.slice_stride = aggregate_slice_elems(q.width, q.height, q.ndisp);
+        // workspace offsets are stored in the pointers for now, rebased later
+        const FrameLayout l = frame_layout(q.width, q.height, q.ndisp, p->npaths, p->p2);
+        f.census_left = reinterpret_cast<uint64_t*>(off);
+        f.census_right = reinterpret_cast<uint64_t*>(off + l.census);
+        f.cost = reinterpret_cast<uint8_t*>(off + 2 * l.census);
+        f.slices = reinterpret_cast<uint8_t*>(off + 2 * l.census + l.cost);
+        f.agg = reinterpret_cast<uint16_t*>(off + 2 * l.census + l.cost + l.slices);
+        f.right_keys = reinterpret_cast<uint32_t*>(off + 2 * l.census + l.cost + l.slices + l.agg);
+        f.disp_left = reinterpret_cast<uint16_t*>(off + 2 * l.census + l.cost + l.slices + l.agg + l.keys);
+        off += l.total;
+        frames->push_back(f);
+    }
+    // launch groups, in stage order
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i) all[i] = i;
+    std::map<int, std::vector<int>> by_d;
+    std::map<std::pair<int, int>, std::vector<int>> by_dv;
+    for (int i = 0; i < n; ++i) {
+        by_d[(*frames)[i].ndisp].push_back(i);
+        by_dv[{(*frames)[i].ndisp, (*frames)[i].variant}].push_back(i);
+    }
+    launches->push_back({kCensus, 0, 0, all});
+    for (auto& kv : by_d) launches->push_back({kCost, kv.first, 0, kv.second});
+    for (auto& kv : by_dv) launches->push_back({kPaths, kv.first.first, kv.first.second, kv.second});
+    launches->push_back({kMerge, 0, 0, all});
+    launches->push_back({kFill, 0, 0, all});
+    for (auto& kv : by_d) launches->push_back({kSelect, kv.first, 0, kv.second});
+    launches->push_back({kMedian, 0, 0, all});
+    // tables: one frame table per launch (frames of the group, in order) and
+    // its block starts
+    *tables_off = off;
+    for (Launch& L : *launches) {
+        L.frames_off = off;
+        off += align256(L.frames.size() * sizeof(Frame));
+        L.starts_off = off;
+        off += align256((L.frames.size() + 1) * sizeof(int32_t));
+    }
+    return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sgm_batch_workspace_bytes(const sgm_pair* pairs, int32_t n, const sgm_params* params) {
+    if (!pairs || n < 1 || !valid_params(params)) return 0;
+    for (int i = 0; i < n; ++i)
+        if (!valid_pair(pairs[i])) return 0;
+    std::vector<Frame> frames;
+    std::vector<Launch> launches;
+    size_t tables_off;
+    return build_layout(pairs, n, params, nullptr, &frames, &launches, &tables_off);
+}
+
+int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n, const sgm_params* params,
+                              void* workspace, size_t workspace_bytes, const char* tune_table,
+                              sgm_plan** plan_out) {
+    if (!plan_out) return SGM_ERR_ARG;
+    *plan_out = nullptr;
+    if (!pairs || n < 1 || !valid_params(params)) return SGM_ERR_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!valid_pair(pairs[i])) return SGM_ERR_ARG;
+    std::vector<Frame> frames;
+    std::vector<Launch> launches;
+    size_t tables_off;
+    const size_t need = build_layout(pairs, n, params, tune_table, &frames, &launches, &tables_off);
+    if (!workspace || workspace_bytes < need) return SGM_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SGM_ERR_ALIGN;
+
+    // rebase the intermediate buffers onto the workspace
+    char* base = static_cast<char*>(workspace);
+    for (Frame& f : frames) {
+        f.census_left = reinterpret_cast<uint64_t*>(base + reinterpret_cast<uintptr_t>(f.census_left));
+        f.census_right = reinterpret_cast<uint64_t*>(base + reinterpret_cast<uintptr_t>(f.census_right));
+        f.cost = reinterpret_cast<uint8_t*>(base + reinterpret_cast<uintptr_t>(f.cost));
+        f.slices = reinterpret_cast<uint8_t*>(base + reinterpret_cast<uintptr_t>(f.slices));
+        f.agg = reinterpret_cast<uint16_t*>(base + reinterpret_cast<uintptr_t>(f.agg));
+        f.right_keys = reinterpret_cast<uint32_t*>(base + reinterpret_cast<uintptr_t>(f.right_keys));
+        f.disp_left = reinterpret_cast<uint16_t*>(base + reinterpret_cast<uintptr_t>(f.disp_left));
+    }
+    // work-list tables: copied to the device once, here
+    std::vector<char> host(need - tables_off, 0);
+    for (Launch& L : launches) {
+        Frame* ft = reinterpret_cast<Frame*>(host.data() + (L.frames_off - tables_off));
+        int32_t* st = reinterpret_cast<int32_t*>(host.data() + (L.starts_off - tables_off));
+        int32_t acc = 0;
+        for (size_t k = 0; k < L.frames.size(); ++k) {
+            ft[k] = frames[L.frames[k]];
+            st[k] = acc;
+            acc += stage_blocks(L.stage, ft[k]);
+        }
+        st[L.frames.size()] = acc;
+        L.wl.frames = reinterpret_cast<const Frame*>(base + L.frames_off);
+        L.wl.starts = reinterpret_cast<const int32_t*>(base + L.starts_off);
+        L.wl.nframes = (int32_t)L.frames.size();
+        L.wl.total = acc;
+    }
+    hipError_t e = hipMemcpy(base + tables_off, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return SGM_ERR_HIP;
+    }
+
+    sgm_plan* plan = new sgm_plan();
+    plan->nframes = n;
+    e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const bool u8 = params->p2 <= 255;
+        hipStream_t s = plan->capture_stream;
+        for (const Launch& L : launches) {
+            hipError_t le = hipSuccess;
+            switch (L.stage) {
+                case kCensus: le = launch_census_batch(L.wl, params->win_w, params->win_h, s); break;
+                case kCost: le = launch_cost_batch(L.wl, L.ndisp, s); break;
+                case kPaths: le = launch_paths_batch(L.wl, L.ndisp, params->npaths, params->p2, L.variant, s); break;
+                case kMerge: le = launch_merge_batch(L.wl, u8, s); break;
+                case kFill: le = launch_fill_keys_batch(L.wl, s); break;
+                case kSelect: le = launch_select_batch(L.wl, L.ndisp, s); break;
+                case kMedian: le = launch_median_batch(L.wl, s); break;
+                default: break;
+            }
+            if (le != hipSuccess && e == hipSuccess) e = le;
+        }
+        hipError_t ce = hipStreamEndCapture(plan->capture_stream, &plan->graph);
+        if (e == hipSuccess) e = ce;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        sgm_batch_plan_destroy(plan);
+        (void)hipGetLastError();
+        return SGM_ERR_HIP;
+    }
+    *plan_out = plan;
+    return SGM_OK;
+}
+
+int32_t sgm_batch_run(sgm_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return SGM_ERR_ARG;
+    const hipError_t e = hipGraphLaunch(plan->exec, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return SGM_ERR_HIP;
+    }
+    return SGM_OK;
+}
+
+int32_t sgm_batch_frames(const sgm_plan* plan) { return plan ? plan->nframes : 0; }
+
+void sgm_batch_plan_destroy(sgm_plan* plan) {
+    if (!plan) return;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    delete plan;
+}
+
+}  // extern "C"

@@ -66,8 +66,15 @@ int32_t sgm_census(const uint8_t* img, int32_t width, int32_t height, int32_t pi
     if (!img || !census_out || bad_size(width, height) || pitch_bytes < width) return SGM_ERR_ARG;
     if (!((win_w == 5 && win_h == 5) || (win_w == 9 && win_h == 7))) return SGM_ERR_UNSUPPORTED;
     if (!aligned(census_out, 8)) return SGM_ERR_ALIGN;
-    return hip_status(sgm::launch_census(img, width, height, pitch_bytes, win_w, win_h,
-                                         census_out, as_stream(stream)));
+    sgm::Frame f{};
+    f.width = width;
+    f.height = height;
+    f.pitch = pitch_bytes;
+    f.win_w = win_w;
+    f.win_h = win_h;
+    f.left = img;
+    f.census_left = census_out;
+    return hip_status(sgm::launch_census(f, false, as_stream(stream)));
 }
 
 int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right, int32_t width,
@@ -76,8 +83,14 @@ int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right, int3
     if (bad_volume(width, height, ndisp)) return SGM_ERR_ARG;
     if (!aligned(census_left, 8) || !aligned(census_right, 8) || !aligned(cost_out, 16))
         return SGM_ERR_ALIGN;
-    return hip_status(sgm::launch_cost(census_left, census_right, width, height, ndisp, cost_out,
-                                       as_stream(stream)));
+    sgm::Frame f{};
+    f.width = width;
+    f.height = height;
+    f.ndisp = ndisp;
+    f.census_left = const_cast<uint64_t*>(census_left);
+    f.census_right = const_cast<uint64_t*>(census_right);
+    f.cost = cost_out;
+    return hip_status(sgm::launch_cost(f, as_stream(stream)));
 }
 
 size_t sgm_aggregate_work_bytes(int32_t width, int32_t height, int32_t ndisp, int32_t npaths,
@@ -95,8 +108,19 @@ int32_t sgm_aggregate(const uint8_t* cost, int32_t width, int32_t height, int32_
     if (!work || work_bytes < sgm::aggregate_work_bytes(width, height, ndisp, npaths, p2))
         return SGM_ERR_WORKSPACE;
     if (!aligned(cost, 16) || !aligned(agg_out, 16) || !aligned(work, 16)) return SGM_ERR_ALIGN;
-    return hip_status(sgm::launch_aggregate(cost, width, height, ndisp, npaths, p1, p2, agg_out,
-                                            work, as_stream(stream)));
+    sgm::Frame f{};
+    f.width = width;
+    f.height = height;
+    f.ndisp = ndisp;
+    f.npaths = npaths;
+    f.p1 = p1;
+    f.p2 = p2;
+    f.variant = 0;
+    f.cost = const_cast<uint8_t*>(cost);
+    f.slices = static_cast<uint8_t*>(work);
+    f.slice_stride = sgm::aggregate_slice_elems(width, height, ndisp);
+    f.agg = agg_out;
+    return hip_status(sgm::launch_aggregate(f, as_stream(stream)));
 }
 
 size_t sgm_wta_lrc_work_elems(int32_t width, int32_t height) {
@@ -114,8 +138,19 @@ int32_t sgm_wta_lrc(const uint16_t* agg, int32_t width, int32_t height, int32_t 
     if (!aligned(agg, 16) || !aligned(disp_out, 4) || !aligned(work, 4) ||
         (disp_right_out && !aligned(disp_right_out, 4)))
         return SGM_ERR_ALIGN;
-    return hip_status(sgm::launch_wta_lrc(agg, width, height, ndisp, lr_tolerance, median3x3,
-                                          disp_out, disp_right_out, work, as_stream(stream)));
+    const size_t n = (size_t)width * height;
+    sgm::Frame f{};
+    f.width = width;
+    f.height = height;
+    f.ndisp = ndisp;
+    f.lr_tolerance = lr_tolerance;
+    f.median3x3 = median3x3;
+    f.agg = const_cast<uint16_t*>(agg);
+    f.right_keys = reinterpret_cast<uint32_t*>(work);          // n uint32
+    f.disp_left = work + 2 * n;                                 // n uint16
+    f.disp = disp_out;
+    f.disp_right = disp_right_out;
+    return hip_status(sgm::launch_wta_lrc(f, as_stream(stream)));
 }
 
 }  // extern "C"

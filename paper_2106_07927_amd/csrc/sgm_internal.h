@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 namespace sgm {
 
@@ -84,18 +87,114 @@ __device__ __forceinline__ uint32_t group_prev(uint32_t v, uint32_t edge, bool f
 }
 
 // ---------------------------------------------------------------------------
-// Host-side launchers (one per kernel family).  All return hipError_t.
+// One stereo frame: sizes, parameters and every device buffer of the path.
+// Single-frame calls fill the fields their stage needs and pass the struct by
+// value; batched launches read an array of them from device memory.
 // ---------------------------------------------------------------------------
-hipError_t launch_census(const uint8_t* img, int width, int height, int pitch,
-                         int win_w, int win_h, uint64_t* out, hipStream_t stream);
-hipError_t launch_cost(const uint64_t* cl, const uint64_t* cr, int width, int height,
-                       int ndisp, uint8_t* cost, hipStream_t stream);
+struct Frame {
+    int32_t width, height, ndisp, pitch;
+    int32_t win_w, win_h, npaths, p1, p2, lr_tolerance, median3x3;
+    int32_t variant;                 // lane-layout variant of the path kernel
+    const uint8_t* left;
+    const uint8_t* right;
+    uint64_t* census_left;
+    uint64_t* census_right;
+    uint8_t* cost;
+    uint8_t* slices;                 // npaths path slices
+    size_t slice_stride;             // elements between slices
+    uint16_t* agg;
+    uint32_t* right_keys;            // D^R keys, width*height
+    uint16_t* disp_left;             // D^L, width*height
+    uint16_t* disp;
+    uint16_t* disp_right;            // may be null
+};
+
+// A launch over several frames: block b of the launch belongs to the frame f
+// with starts[f] <= b < starts[f + 1] and is its block b - starts[f].
+struct WorkList {
+    const Frame* frames;
+    const int32_t* starts;           // nframes + 1 entries
+    int32_t nframes;
+    int32_t total;                   // starts[nframes]
+};
+
+__device__ __forceinline__ int find_frame(const WorkList& wl, int b) {
+    int lo = 0, hi = wl.nframes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (wl.starts[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Grid of a persistent launch: enough blocks to fill the GPU, never more than
+// there is work.
+inline int persistent_grid(int total_blocks, int per_cu = 8) {
+    return std::max(1, std::min(total_blocks, 256 * per_cu));
+}
+
+// ---------------------------------------------------------------------------
+// Stage geometry (blocks per frame), shared by host planning and kernels.
+// ---------------------------------------------------------------------------
+constexpr int kCensusTileW = 64;
+constexpr int kCensusTileH = 16;
+__host__ __device__ inline int census_blocks_x(int w) { return (w + kCensusTileW - 1) / kCensusTileW; }
+__host__ __device__ inline int census_blocks(int w, int h) {
+    return census_blocks_x(w) * ((h + kCensusTileH - 1) / kCensusTileH);
+}
+
+constexpr int kCostPix = 128;
+__host__ __device__ inline int cost_blocks_x(int w) { return (w + kCostPix - 1) / kCostPix; }
+
+constexpr int kSelectSeg = 128;   // pixels per wave segment
+constexpr int kSelectWaves = 4;
+__host__ __device__ inline int select_blocks_x(int w) {
+    const int segs = (w + kSelectSeg - 1) / kSelectSeg;
+    return (segs + kSelectWaves - 1) / kSelectWaves;
+}
+
+constexpr int kMedianTileW = 64;
+constexpr int kMedianTileH = 4;
+__host__ __device__ inline int median_blocks_x(int w) { return (w + kMedianTileW - 1) / kMedianTileW; }
+__host__ __device__ inline int median_blocks(int w, int h) {
+    return median_blocks_x(w) * ((h + kMedianTileH - 1) / kMedianTileH);
+}
+
+constexpr int kMergeChunk = 256 * 16;     // elements per merge block
+__host__ __device__ inline int merge_blocks(size_t n) { return (int)((n + kMergeChunk - 1) / kMergeChunk); }
+
+constexpr int kFillChunk = 256 * 16;
+__host__ __device__ inline int fill_blocks(size_t n) { return (int)((n + kFillChunk - 1) / kFillChunk); }
+
+// Lane layout of the path kernel for one disparity range and variant.
+struct PathLayout {
+    int nreg_h, lpl_h;    // horizontal lines
+    int nreg_o, lpl_o;    // vertical and diagonal lines
+};
+int path_variants(int ndisp);                       // number of variants (>= 1)
+PathLayout path_layout(int ndisp, int variant);
+int path_blocks(int width, int height, int ndisp, int npaths, int variant);
+size_t aggregate_slice_elems(int width, int height, int ndisp);
 size_t aggregate_work_bytes(int width, int height, int ndisp, int npaths, int p2);
-hipError_t launch_aggregate(const uint8_t* cost, int width, int height, int ndisp,
-                            int npaths, int p1, int p2, uint16_t* agg, void* work,
-                            hipStream_t stream);
-hipError_t launch_wta_lrc(const uint16_t* agg, int width, int height, int ndisp,
-                          int lr_tolerance, int median3x3, uint16_t* disp,
-                          uint16_t* disp_right, uint16_t* work, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Launchers.  Single-frame forms take the frame by value; batched forms take
+// a work list whose frames all share the template parameters of the stage
+// (same window for census, same D for cost / paths / select).
+// ---------------------------------------------------------------------------
+hipError_t launch_census(const Frame& f, bool right, hipStream_t stream);
+hipError_t launch_cost(const Frame& f, hipStream_t stream);
+hipError_t launch_aggregate(const Frame& f, hipStream_t stream);
+hipError_t launch_wta_lrc(const Frame& f, hipStream_t stream);
+
+hipError_t launch_census_batch(const WorkList& wl, int win_w, int win_h, hipStream_t stream);
+hipError_t launch_cost_batch(const WorkList& wl, int ndisp, hipStream_t stream);
+hipError_t launch_paths_batch(const WorkList& wl, int ndisp, int npaths, int p2, int variant,
+                              hipStream_t stream);
+hipError_t launch_merge_batch(const WorkList& wl, bool u8, hipStream_t stream);
+hipError_t launch_fill_keys_batch(const WorkList& wl, hipStream_t stream);
+hipError_t launch_select_batch(const WorkList& wl, int ndisp, hipStream_t stream);
+hipError_t launch_median_batch(const WorkList& wl, hipStream_t stream);
 
 }  // namespace sgm

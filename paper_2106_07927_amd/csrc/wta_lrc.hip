@@ -29,8 +29,6 @@ namespace {
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr uint16_t kInvalid = 0xFFFFu;
-constexpr int kSeg = 128;          // pixels per wave segment
-constexpr int kSegWaves = 4;
 
 __device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t edge) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xF, 0xF, false);
@@ -81,17 +79,21 @@ __device__ __forceinline__ uint32_t pick(const uint32_t (&T)[EPL], int e) {
     return r;
 }
 
+struct SelectTile {
+    uint32_t key[kSelectWaves][64][65];
+};
+
+// Segment of one wave: block (bx, y) of one frame; waves are independent.
 template <int EPL, bool VEC>
-__global__ __launch_bounds__(64 * kSegWaves) void select_kernel(const uint16_t* __restrict__ agg,
-                                                                int width, int ndisp,
-                                                                uint16_t* __restrict__ disp_left,
-                                                                uint32_t* __restrict__ right_keys) {
+__device__ __forceinline__ void select_block(SelectTile& st, const uint16_t* __restrict__ agg,
+                                             int width, int ndisp,
+                                             uint16_t* __restrict__ disp_left,
+                                             uint32_t* __restrict__ right_keys, int bx, int y) {
     constexpr int K = 16;                      // pixels per load chunk
-    __shared__ uint32_t tile[kSegWaves][64][65];
+    constexpr int kSeg = kSelectSeg;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int seg = blockIdx.x * kSegWaves + wave;
-    const int y = blockIdx.y;
+    const int seg = bx * kSelectWaves + wave;
     const int x0 = seg * kSeg;
     if (x0 >= width) return;                       // uniform per wave
     const int x1 = min(width, x0 + kSeg);
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void select_kernel(const uint16_t* 
     const int d0 = lane * EPL;
     const int dlast_lane = (ndisp - 1) / EPL;
     const int dlast_e = (ndisp - 1) % EPL;
-    uint32_t (*tl)[65] = tile[wave];
+    uint32_t (*tl)[65] = st.key[wave];
 
     uint32_t T[EPL];
 #pragma unroll
@@ -175,9 +177,38 @@ __global__ __launch_bounds__(64 * kSegWaves) void select_kernel(const uint16_t* 
     }
 }
 
-__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t v) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+template <int EPL, bool VEC>
+__global__ __launch_bounds__(64 * kSelectWaves) void select_kernel(Frame f) {
+    __shared__ SelectTile st;
+    select_block<EPL, VEC>(st, f.agg, f.width, f.ndisp, f.disp_left, f.right_keys, blockIdx.x, blockIdx.y);
+}
+
+template <int EPL, bool VEC>
+__global__ __launch_bounds__(64 * kSelectWaves) void select_batch_kernel(WorkList wl) {
+    __shared__ SelectTile st;
+    for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
+        const int fi = find_frame(wl, b);
+        const Frame& f = wl.frames[fi];
+        const int lb = b - wl.starts[fi];
+        const int bxs = select_blocks_x(f.width);
+        select_block<EPL, VEC>(st, f.agg, f.width, f.ndisp, f.disp_left, f.right_keys, lb % bxs, lb / bxs);
+    }
+}
+
+// D^R keys start at "no candidate" (all ones).
+__device__ __forceinline__ void fill_keys_block(const Frame& f, int lb) {
+    const size_t n = (size_t)f.width * f.height;
+    const size_t e0 = (size_t)lb * kFillChunk;
+    for (size_t e = e0 + threadIdx.x; e < n && e < e0 + kFillChunk; e += blockDim.x) f.right_keys[e] = kInf;
+}
+
+__global__ __launch_bounds__(256) void fill_keys_kernel(Frame f) { fill_keys_block(f, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void fill_keys_batch_kernel(WorkList wl) {
+    for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
+        const int fi = find_frame(wl, b);
+        fill_keys_block(wl.frames[fi], b - wl.starts[fi]);
+    }
 }
 
 // Median of nine by the first five passes of a bubble-sort network (App. F).
@@ -195,16 +226,19 @@ __device__ __forceinline__ uint32_t median9(uint32_t v[9]) {
     return v[4];
 }
 
-constexpr int kTW = 64, kTH = 4;
+constexpr int kTW = kMedianTileW, kTH = kMedianTileH;
 
-__global__ __launch_bounds__(256) void check_median_kernel(const uint16_t* __restrict__ disp_left,
-                                                           const uint32_t* __restrict__ right_keys,
-                                                           int width, int height, int tolerance,
-                                                           int median,
-                                                           uint16_t* __restrict__ disp,
-                                                           uint16_t* __restrict__ disp_right) {
-    __shared__ uint16_t tile[(kTH + 2) * (kTW + 2)];
-    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
+struct MedianTile {
+    uint16_t v[(kTH + 2) * (kTW + 2)];
+};
+
+__device__ __forceinline__ void check_median_block(MedianTile& mt, const uint16_t* __restrict__ disp_left,
+                                                   const uint32_t* __restrict__ right_keys,
+                                                   int width, int height, int tolerance, int median,
+                                                   uint16_t* __restrict__ disp,
+                                                   uint16_t* __restrict__ disp_right, int bx, int by) {
+    uint16_t* tile = mt.v;
+    const int x0 = bx * kTW, y0 = by * kTH;
     for (int i = threadIdx.x; i < (kTH + 2) * (kTW + 2); i += 256) {
         const int ly = i / (kTW + 2), lx = i - ly * (kTW + 2);
         const int gx = x0 + lx - 1, gy = y0 + ly - 1;
@@ -228,51 +262,92 @@ __global__ __launch_bounds__(256) void check_median_kernel(const uint16_t* __res
     __syncthreads();
     const int tx = threadIdx.x & (kTW - 1), ty = threadIdx.x / kTW;
     const int gx = x0 + tx, gy = y0 + ty;
-    if (gx >= width || gy >= height) return;
-    const uint16_t* c = &tile[(ty + 1) * (kTW + 2) + tx + 1];
-    uint16_t out = *c;
-    if (median && out != kInvalid) {
-        uint32_t v[9];
-        int k = 0;
+    if (gx < width && gy < height) {
+        const uint16_t* c = &tile[(ty + 1) * (kTW + 2) + tx + 1];
+        uint16_t out = *c;
+        if (median && out != kInvalid) {
+            uint32_t v[9];
+            int k = 0;
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
+            for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) v[k++] = c[dy * (kTW + 2) + dx];
-        out = (uint16_t)median9(v);
+                for (int dx = -1; dx <= 1; ++dx) v[k++] = c[dy * (kTW + 2) + dx];
+            out = (uint16_t)median9(v);
+        }
+        const size_t idx = (size_t)gy * width + gx;
+        disp[idx] = out;
+        if (disp_right) disp_right[idx] = (uint16_t)(right_keys[idx] & 0xFFu);
     }
-    const size_t idx = (size_t)gy * width + gx;
-    disp[idx] = out;
-    if (disp_right) disp_right[idx] = (uint16_t)(right_keys[idx] & 0xFFu);
+    __syncthreads();   // the tile is reused by the next work item
+}
+
+__global__ __launch_bounds__(256) void check_median_kernel(Frame f) {
+    __shared__ MedianTile mt;
+    check_median_block(mt, f.disp_left, f.right_keys, f.width, f.height, f.lr_tolerance,
+                       f.median3x3, f.disp, f.disp_right, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void check_median_batch_kernel(WorkList wl) {
+    __shared__ MedianTile mt;
+    for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
+        const int fi = find_frame(wl, b);
+        const Frame& f = wl.frames[fi];
+        const int lb = b - wl.starts[fi];
+        const int bxs = median_blocks_x(f.width);
+        check_median_block(mt, f.disp_left, f.right_keys, f.width, f.height, f.lr_tolerance,
+                           f.median3x3, f.disp, f.disp_right, lb % bxs, lb / bxs);
+    }
+}
+
+template <int EPL, bool VEC>
+void launch_select_t(const Frame* one, const WorkList* wl, hipStream_t stream) {
+    if (one) {
+        const dim3 g(select_blocks_x(one->width), one->height);
+        select_kernel<EPL, VEC><<<g, 64 * kSelectWaves, 0, stream>>>(*one);
+    } else {
+        select_batch_kernel<EPL, VEC><<<persistent_grid(wl->total, 2), 64 * kSelectWaves, 0, stream>>>(*wl);
+    }
+}
+
+void launch_select_any(const Frame* one, const WorkList* wl, int ndisp, hipStream_t stream) {
+    if (ndisp <= 64) {
+        launch_select_t<1, true>(one, wl, stream);
+    } else if (ndisp <= 128) {
+        if (ndisp % 2 == 0) launch_select_t<2, true>(one, wl, stream);
+        else launch_select_t<2, false>(one, wl, stream);
+    } else {
+        if (ndisp % 4 == 0) launch_select_t<4, true>(one, wl, stream);
+        else launch_select_t<4, false>(one, wl, stream);
+    }
 }
 
 }  // namespace
 
-hipError_t launch_wta_lrc(const uint16_t* agg, int width, int height, int ndisp,
-                          int lr_tolerance, int median3x3, uint16_t* disp,
-                          uint16_t* disp_right, uint16_t* work, hipStream_t stream) {
-    const size_t n = (size_t)width * height;
-    uint32_t* keys = reinterpret_cast<uint32_t*>(work);     // n uint32
-    uint16_t* dl = work + 2 * n;                              // n uint16
-    {
-        const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
-        fill_u32_kernel<<<blocks, 256, 0, stream>>>(keys, n, kInf);
-    }
-    const int segs = (width + kSeg - 1) / kSeg;
-    const dim3 g1((segs + kSegWaves - 1) / kSegWaves, height);
-    if (ndisp <= 64) {
-        select_kernel<1, true><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
-    } else if (ndisp <= 128) {
-        if (ndisp % 2 == 0) select_kernel<2, true><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
-        else select_kernel<2, false><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
-    } else {
-        if (ndisp % 4 == 0) select_kernel<4, true><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
-        else select_kernel<4, false><<<g1, 64 * kSegWaves, 0, stream>>>(agg, width, ndisp, dl, keys);
-    }
+hipError_t launch_wta_lrc(const Frame& f, hipStream_t stream) {
+    const size_t n = (size_t)f.width * f.height;
+    fill_keys_kernel<<<fill_blocks(n), 256, 0, stream>>>(f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 g2((width + kTW - 1) / kTW, (height + kTH - 1) / kTH);
-    check_median_kernel<<<g2, 256, 0, stream>>>(dl, keys, width, height, lr_tolerance,
-                                                 median3x3, disp, disp_right);
+    launch_select_any(&f, nullptr, f.ndisp, stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2(median_blocks_x(f.width), (f.height + kTH - 1) / kTH);
+    check_median_kernel<<<g2, 256, 0, stream>>>(f);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_keys_batch(const WorkList& wl, hipStream_t stream) {
+    fill_keys_batch_kernel<<<persistent_grid(wl.total), 256, 0, stream>>>(wl);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_batch(const WorkList& wl, int ndisp, hipStream_t stream) {
+    launch_select_any(nullptr, &wl, ndisp, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_median_batch(const WorkList& wl, hipStream_t stream) {
+    check_median_batch_kernel<<<persistent_grid(wl.total), 256, 0, stream>>>(wl);
     return hipGetLastError();
 }
 

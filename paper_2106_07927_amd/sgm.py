@@ -29,7 +29,23 @@ SGM_ERR_HIP = -4
 SGM_ERR_WORKSPACE = -5
 
 EXPORTS = ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_aggregate_work_bytes", "sgm_wta_lrc",
-           "sgm_wta_lrc_work_elems", "sgm_status_string", "sgm_last_hip_error", "sgm_abi_version")
+           "sgm_wta_lrc_work_elems", "sgm_batch_workspace_bytes", "sgm_batch_plan_create",
+           "sgm_batch_run", "sgm_batch_frames", "sgm_batch_plan_destroy", "sgm_status_string",
+           "sgm_last_hip_error", "sgm_abi_version")
+
+
+class SgmParams(ctypes.Structure):
+    """sgm_params of include/sgm.h."""
+    _fields_ = [("win_w", ctypes.c_int32), ("win_h", ctypes.c_int32), ("npaths", ctypes.c_int32),
+                ("p1", ctypes.c_int32), ("p2", ctypes.c_int32), ("lr_tolerance", ctypes.c_int32),
+                ("median3x3", ctypes.c_int32)]
+
+
+class SgmPair(ctypes.Structure):
+    """sgm_pair of include/sgm.h."""
+    _fields_ = [("left", ctypes.c_void_p), ("right", ctypes.c_void_p), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("pitch_bytes", ctypes.c_int32), ("ndisp", ctypes.c_int32),
+                ("disp_out", ctypes.c_void_p), ("disp_right_out", ctypes.c_void_p)]
 
 
 class SGMError(RuntimeError):
@@ -60,6 +76,18 @@ def load_library(path: str = LIB_PATH):
     lib.sgm_wta_lrc.argtypes = [P, I32, I32, I32, I32, I32, P, P, P, P]
     lib.sgm_wta_lrc_work_elems.argtypes = [I32, I32]
     lib.sgm_wta_lrc_work_elems.restype = ctypes.c_size_t
+    PP = ctypes.POINTER(SgmPair)
+    lib.sgm_batch_workspace_bytes.argtypes = [PP, I32, ctypes.POINTER(SgmParams)]
+    lib.sgm_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.sgm_batch_plan_create.argtypes = [PP, I32, ctypes.POINTER(SgmParams), P, ctypes.c_size_t,
+                                          ctypes.c_char_p, ctypes.POINTER(P)]
+    lib.sgm_batch_plan_create.restype = I32
+    lib.sgm_batch_run.argtypes = [P, P]
+    lib.sgm_batch_run.restype = I32
+    lib.sgm_batch_frames.argtypes = [P]
+    lib.sgm_batch_frames.restype = I32
+    lib.sgm_batch_plan_destroy.argtypes = [P]
+    lib.sgm_batch_plan_destroy.restype = None
     lib.sgm_status_string.argtypes = [I32]
     lib.sgm_status_string.restype = ctypes.c_char_p
     lib.sgm_last_hip_error.argtypes = []
@@ -231,3 +259,69 @@ class StereoSGM:
         sgm_wta_lrc(self.agg, p.lr_tolerance, p.median3x3, out=self.disp,
                     out_right=self.disp_right, work=self.work, stream=stream)
         return self.disp
+
+
+def _params_struct(p: Params) -> SgmParams:
+    return SgmParams(p.win_w, p.win_h, p.npaths, p.p1, p.p2, p.lr_tolerance, int(bool(p.median3x3)))
+
+
+class BatchPlan:
+    """Many pairs of uneven size and disparity range as one captured hipGraph.
+
+    lefts / rights: uint8 [H][W] device tensors (kept alive by the plan);
+    ndisps: disparity range per pair.  Outputs: self.disp[i] (and
+    self.disp_right[i] if want_right), uint16 [H][W].  run() enqueues one
+    graph launch; the inputs may be overwritten in place between runs.
+    """
+
+    def __init__(self, lefts, rights, ndisps, params: Params, tune_table: Optional[str] = None,
+                 want_right: bool = False):
+        lib = load_library()
+        n = len(lefts)
+        if not (n == len(rights) == len(ndisps)) or n < 1:
+            raise ValueError("lefts, rights and ndisps must have the same, non-zero length")
+        self.lefts, self.rights, self.params = list(lefts), list(rights), params
+        dev = self.lefts[0].device
+        self.disp, self.disp_right = [], []
+        pairs = (SgmPair * n)()
+        for i, (l, r, nd) in enumerate(zip(self.lefts, self.rights, ndisps)):
+            if l.dtype != torch.uint8 or l.dim() != 2 or l.shape != r.shape or r.dtype != torch.uint8:
+                raise ValueError(f"pair {i}: expected two uint8 [H][W] tensors of one shape")
+            h, w = l.shape
+            d = _empty((h, w), torch.uint16, dev)
+            dr = _empty((h, w), torch.uint16, dev) if want_right else None
+            self.disp.append(d)
+            self.disp_right.append(dr)
+            pairs[i] = SgmPair(_ptr(l).value, _ptr(r).value, w, h, w, int(nd), _ptr(d).value,
+                               _ptr(dr).value if dr is not None else None)
+        self._pairs = pairs
+        prm = _params_struct(params)
+        need = int(lib.sgm_batch_workspace_bytes(pairs, n, ctypes.byref(prm)))
+        if need == 0:
+            raise ValueError("invalid batch (sizes, disparity ranges or parameters)")
+        self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        offset = (-base) % 256
+        handle = ctypes.c_void_p()
+        table = tune_table.encode() if tune_table else None
+        _check(lib.sgm_batch_plan_create(pairs, n, ctypes.byref(prm),
+                                         ctypes.c_void_p(base + offset), need, table,
+                                         ctypes.byref(handle)))
+        self._handle = handle
+        self.n = n
+
+    def run(self, stream=None):
+        if not self._handle:
+            raise RuntimeError("plan destroyed")
+        _check(load_library().sgm_batch_run(self._handle, _stream(stream)))
+
+    def close(self):
+        if self._handle:
+            load_library().sgm_batch_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

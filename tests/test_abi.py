@@ -115,3 +115,44 @@ def test_python_binding_rejects_host_tensors(lib):
     img = torch.zeros(4, 4, dtype=torch.uint8)
     with pytest.raises(ValueError):
         sgm.sgm_census(img, 5, 5, out=torch.zeros(4, 4, dtype=torch.uint64))
+
+
+def test_batch_validation(lib):
+    prm = sgm.SgmParams(9, 7, 8, 10, 120, 1, 1)
+    pairs = (sgm.SgmPair * 2)()
+    pairs[0] = sgm.SgmPair(FAKE, FAKE, 64, 48, 64, 64, FAKE, None)
+    pairs[1] = sgm.SgmPair(FAKE, FAKE, 32, 16, 40, 16, FAKE, FAKE)
+    need = lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(prm))
+    # two frames of intermediates (census x2, cost, slices, agg, keys, D^L) plus tables
+    n0, n1 = 64 * 48, 32 * 16
+    lower = sum(8 * 2 * n + n * nd + 8 * n * nd + 2 * n * nd + 4 * n + 2 * n
+                for n, nd in ((n0, 64), (n1, 16)))
+    assert need >= lower
+    assert lib.sgm_batch_workspace_bytes(pairs, 0, ctypes.byref(prm)) == 0
+    bad = sgm.SgmParams(7, 9, 8, 10, 120, 1, 1)                      # window
+    assert lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(bad)) == 0
+    bad = sgm.SgmParams(9, 7, 8, 121, 120, 1, 1)                     # p1 > p2
+    assert lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(bad)) == 0
+    handle = ctypes.c_void_p()
+    pairs[1].pitch_bytes = 31                                        # pitch < width
+    assert lib.sgm_batch_plan_create(pairs, 2, ctypes.byref(prm), P(FAKE), need, None,
+                                     ctypes.byref(handle)) == ARG
+    pairs[1].pitch_bytes = 40
+    pairs[0].ndisp = 0
+    assert lib.sgm_batch_plan_create(pairs, 2, ctypes.byref(prm), P(FAKE), need, None,
+                                     ctypes.byref(handle)) == ARG
+    pairs[0].ndisp = 64
+    pairs[0].disp_out = FAKE + 2                                     # misaligned output
+    assert lib.sgm_batch_plan_create(pairs, 2, ctypes.byref(prm), P(FAKE), need, None,
+                                     ctypes.byref(handle)) == ARG
+    pairs[0].disp_out = FAKE
+    assert lib.sgm_batch_plan_create(pairs, 2, ctypes.byref(prm), P(NULL), need, None,
+                                     ctypes.byref(handle)) == WS
+    assert lib.sgm_batch_plan_create(pairs, 2, ctypes.byref(prm), P(FAKE), need - 1, None,
+                                     ctypes.byref(handle)) == WS
+    assert lib.sgm_batch_plan_create(pairs, 2, ctypes.byref(prm), P(FAKE + 16), need, None,
+                                     ctypes.byref(handle)) == ALIGN
+    assert not handle.value
+    assert lib.sgm_batch_run(None, None) == ARG
+    assert lib.sgm_batch_frames(None) == 0
+    lib.sgm_batch_plan_destroy(None)

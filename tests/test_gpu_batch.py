@@ -1,0 +1,170 @@
+"""GPU: the batched form.  Every pair of a batch (one hipGraph launch) is
+bit-identical to its plain per-frame result through the four ABI calls and
+to the oracle; graph replays with eager work and input changes in between
+stay exact; every path-kernel lane-layout variant gives identical bits."""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_07927_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2106_07927_amd import sgm
+    sgm.load_library()
+    return torch, torch.device("cuda:0")
+
+
+PARAMS = dict(win_w=9, win_h=7, npaths=8, p1=10, p2=120, lr_tolerance=1, median3x3=True)
+SHAPES = [(64, 48, 16), (130, 40, 64), (200, 96, 128), (97, 33, 7), (321, 17, 256), (1, 1, 1),
+          (150, 60, 128), (66, 70, 64)]
+
+
+def single(sgm, torch, l, r, nd, prm):
+    eng = sgm.StereoSGM(l.shape[1], l.shape[0], prm, device=l.device)
+    eng.run(l, r)
+    torch.cuda.synchronize()
+    return eng.disp.cpu().numpy(), eng.disp_right.cpu().numpy()
+
+
+def make_inputs(torch, dev, shapes, seed):
+    lefts, rights, host = [], [], []
+    for i, (w, h, nd) in enumerate(shapes):
+        a, b = datagen.random_images(w, h, seed=seed + i)
+        host.append((a, b))
+        lefts.append(torch.from_numpy(a).to(dev))
+        rights.append(torch.from_numpy(b).to(dev))
+    return lefts, rights, host
+
+
+def test_batch_matches_single_frame_and_oracle(torch_dev):
+    torch, dev = torch_dev
+    from paper_2106_07927_amd import sgm
+    say("batch vs single vs oracle")
+    prm = sgm.Params(ndisp=0, **PARAMS)
+    lefts, rights, host = make_inputs(torch, dev, SHAPES, seed=900)
+    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in SHAPES], prm, want_right=True)
+    plan.run()
+    torch.cuda.synchronize()
+    for i, (w, h, nd) in enumerate(SHAPES):
+        d_single, dr_single = single(sgm, torch, lefts[i], rights[i], nd,
+                                     sgm.Params(ndisp=nd, **PARAMS))
+        np.testing.assert_array_equal(plan.disp[i].cpu().numpy(), d_single, err_msg=f"pair {i}")
+        np.testing.assert_array_equal(plan.disp_right[i].cpu().numpy(), dr_single, err_msg=f"pair {i}")
+        ref = oracle.run(host[i][0], host[i][1], oracle.Params(ndisp=nd, **PARAMS))
+        np.testing.assert_array_equal(d_single, ref["disp"], err_msg=f"pair {i} vs oracle")
+    plan.close()
+
+
+def test_batch_graph_replays(torch_dev):
+    torch, dev = torch_dev
+    from paper_2106_07927_amd import sgm
+    say("batch graph replays")
+    shapes = SHAPES[:5]
+    prm = sgm.Params(ndisp=0, **PARAMS)
+    lefts, rights, _ = make_inputs(torch, dev, shapes, seed=1000)
+    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in shapes], prm)
+    plan.run()
+    torch.cuda.synchronize()
+    first = [d.cpu().numpy() for d in plan.disp]
+    for rep in range(3):
+        # eager work between replays: unrelated single-frame calls and torch ops
+        single(sgm, torch, lefts[2], rights[2], shapes[2][2], sgm.Params(ndisp=shapes[2][2], **PARAMS))
+        junk = torch.zeros(1 << 20, dtype=torch.int32, device=dev).sum()
+        for d in plan.disp:
+            d.fill_(7)
+        plan.run()
+        torch.cuda.synchronize()
+        for i in range(len(shapes)):
+            np.testing.assert_array_equal(plan.disp[i].cpu().numpy(), first[i], err_msg=f"replay {rep}")
+    # new images in the same buffers: the replay reads them
+    new_l, new_r, _ = make_inputs(torch, dev, shapes, seed=2000)
+    for i in range(len(shapes)):
+        lefts[i].copy_(new_l[i])
+        rights[i].copy_(new_r[i])
+    plan.run()
+    torch.cuda.synchronize()
+    for i, (w, h, nd) in enumerate(shapes):
+        d_single, _ = single(sgm, torch, new_l[i], new_r[i], nd, sgm.Params(ndisp=nd, **PARAMS))
+        np.testing.assert_array_equal(plan.disp[i].cpu().numpy(), d_single)
+    plan.close()
+
+
+def test_batch_every_variant_gives_same_bits(torch_dev):
+    torch, dev = torch_dev
+    from paper_2106_07927_amd import sgm
+    say("batch variants")
+    shapes = [(200, 96, 128), (130, 40, 64), (100, 50, 256), (90, 30, 48)]
+    prm = sgm.Params(ndisp=0, **PARAMS)
+    lefts, rights, _ = make_inputs(torch, dev, shapes, seed=3000)
+    results = []
+    for v in range(3):
+        table = json.dumps({f"{w}x{h}x{nd}": v for (w, h, nd) in shapes})
+        plan = sgm.BatchPlan(lefts, rights, [s[2] for s in shapes], prm, tune_table=table)
+        plan.run()
+        torch.cuda.synchronize()
+        results.append([d.cpu().numpy() for d in plan.disp])
+        plan.close()
+    for v in (1, 2):
+        for i in range(len(shapes)):
+            np.testing.assert_array_equal(results[v][i], results[0][i], err_msg=f"variant {v} pair {i}")
+
+
+def test_batch_4path_5x5_and_u16_slices(torch_dev):
+    torch, dev = torch_dev
+    from paper_2106_07927_amd import sgm
+    say("batch 4-path 5x5, and P2 > 255")
+    shapes = [(120, 64, 64), (77, 31, 32)]
+    lefts, rights, host = make_inputs(torch, dev, shapes, seed=4000)
+    for extra in (dict(win_w=5, win_h=5, npaths=4, p1=7, p2=86, lr_tolerance=-1, median3x3=False),
+                  dict(win_w=9, win_h=7, npaths=8, p1=30, p2=900, lr_tolerance=1, median3x3=True)):
+        prm = sgm.Params(ndisp=0, **extra)
+        plan = sgm.BatchPlan(lefts, rights, [s[2] for s in shapes], prm)
+        plan.run()
+        torch.cuda.synchronize()
+        for i, (w, h, nd) in enumerate(shapes):
+            ref = oracle.run(host[i][0], host[i][1], oracle.Params(ndisp=nd, **extra))
+            np.testing.assert_array_equal(plan.disp[i].cpu().numpy(), ref["disp"])
+        plan.close()
+
+
+def test_batch_mixed_workload_matches_plain(torch_dev):
+    """The 64-pair mixed batch (sizes from 320x240 to 1920x1080, D from 64
+    to 256): each pair bit-identical to its plain per-frame result."""
+    torch, dev = torch_dev
+    from paper_2106_07927_amd import sgm
+    say("64-pair mixed batch")
+    specs = datagen.batch_specs()
+    prm = sgm.Params(ndisp=0, **PARAMS)
+    lefts, rights = [], []
+    for (w, h, nd, seed) in specs:
+        a, b = datagen.random_images(w, h, seed=seed)
+        lefts.append(torch.from_numpy(a).to(dev))
+        rights.append(torch.from_numpy(b).to(dev))
+    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in specs], prm)
+    plan.run()
+    torch.cuda.synchronize()
+    engines = {}
+    for i, (w, h, nd, _) in enumerate(specs):
+        key = (w, h, nd)
+        if key not in engines:
+            engines[key] = sgm.StereoSGM(w, h, sgm.Params(ndisp=nd, **PARAMS), device=dev)
+        eng = engines[key]
+        eng.run(lefts[i], rights[i])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(plan.disp[i].cpu().numpy(), eng.disp.cpu().numpy(),
+                                      err_msg=f"pair {i} {key}")
+    plan.close()
