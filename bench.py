@@ -37,7 +37,93 @@ def parse():
     ap.add_argument("--workload", default="c2_1242x375_d128_r8")
     ap.add_argument("--cpu-frames", type=int, default=3,
                     help="frames of the CPU-oracle sample (0 skips it)")
+    ap.add_argument("--batch-reps", type=int, default=5,
+                    help="timed replays of the 64-pair batch (0 skips the batched form)")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="length of the served trace (0 skips the served form)")
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     return ap.parse_args()
+
+
+def batched_form(args, torch, dev, sgm, datagen):
+    """64 mixed pairs: one hipGraph replay per batch vs 64 plain per-frame
+    pipelines on one stream."""
+    from paper_2106_07927_amd import tune
+    specs = datagen.batch_specs()
+    base = datagen.CONFIGS["c2_1242x375_d128_r8"]
+    params = sgm.Params(ndisp=0, win_w=base["win_w"], win_h=base["win_h"], npaths=base["npaths"],
+                        p1=base["p1"], p2=base["p2"], lr_tolerance=base["lr_tolerance"],
+                        median3x3=base["median3x3"])
+    lefts, rights = [], []
+    for (w, h, nd, seed) in specs:
+        pair = datagen.make_pair(w, h, nd, seed, base["planes"], base["occlusion"])
+        lefts.append(torch.from_numpy(pair["left"]).to(dev))
+        rights.append(torch.from_numpy(pair["right"]).to(dev))
+    table, tune_ms = tune.tune([(w, h, nd) for (w, h, nd, _) in specs], params, device=dev)
+    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in specs], params, tune_table=json.dumps(table))
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.batch_reps):
+        plan.run()
+    t1.record()
+    torch.cuda.synchronize()
+    batch_ms = t0.elapsed_time(t1) / args.batch_reps
+    plan.close()
+    del plan
+    engines = {}
+    for (w, h, nd, _) in specs:
+        if (w, h, nd) not in engines:
+            engines[(w, h, nd)] = sgm.StereoSGM(w, h, sgm.Params(**{**params.__dict__, "ndisp": nd}), device=dev)
+
+    def plain():
+        for i, (w, h, nd, _) in enumerate(specs):
+            engines[(w, h, nd)].run(lefts[i], rights[i])
+
+    plain()
+    torch.cuda.synchronize()
+    t0.record()
+    reps = max(1, args.batch_reps // 2)
+    for _ in range(reps):
+        plain()
+    t1.record()
+    torch.cuda.synchronize()
+    plain_ms = t0.elapsed_time(t1) / reps
+    des = sum(w * h * nd for (w, h, nd, _) in specs)
+    del engines
+    torch.cuda.empty_cache()
+    return {"pairs": len(specs), "des_per_batch": des,
+            "ms_per_batch": round(batch_ms, 3), "mdes": round(des / batch_ms / 1e3, 1),
+            "fps": round(len(specs) / batch_ms * 1e3, 1),
+            "plain_ms_per_batch": round(plain_ms, 3), "plain_mdes": round(des / plain_ms / 1e3, 1),
+            "speedup": round(plain_ms / batch_ms, 3), "tune_table": table, "tune_ms": tune_ms,
+            "launch": "one hipGraph replay (persistent work-list kernels per stage)"}
+
+
+def served_form(args, torch, sgm, datagen):
+    """16 Poisson camera streams at 30 Hz: continuous batching vs plain FIFO."""
+    from paper_2106_07927_amd import serve
+    base = datagen.CONFIGS["c2_1242x375_d128_r8"]
+    params = sgm.Params(ndisp=0, win_w=base["win_w"], win_h=base["win_h"], npaths=base["npaths"],
+                        p1=base["p1"], p2=base["p2"], lr_tolerance=base["lr_tolerance"],
+                        median3x3=base["median3x3"])
+    specs = [serve.StreamSpec(*s) for s in datagen.stream_specs()]
+    backend = serve.GpuBackend(specs, params, frames_per_stream=2)
+    trace = serve.make_trace(specs, 30.0, args.serve_seconds, 2, seed=2110)
+    budget = int(args.serve_budget_gib * 2 ** 30)
+    mix = serve.Server(specs, backend, budget_bytes=budget, hip_streams=8).run(trace)
+    torch.cuda.synchronize()
+    tight = serve.Server(specs, backend, budget_bytes=8 * 2 ** 30, hip_streams=8).run(trace)
+    torch.cuda.synchronize()
+    fifo = serve.serve_plain(trace, specs, backend)
+    torch.cuda.synchronize()
+    offered = sum(s.width * s.height * s.ndisp for s in specs) * 30.0 / 1e6
+    return {"streams": len(specs), "rate_hz": 30.0, "seconds": args.serve_seconds,
+            "offered_mdes": round(offered, 1), "budget_gib": args.serve_budget_gib,
+            "continuous": mix.summary(specs), "tight_budget_8gib": tight.summary(specs),
+            "plain_fifo": fifo.summary(specs)}
 
 
 def cpu_baseline(pair, cfg, frames):
@@ -161,6 +247,12 @@ def main():
                           "hardware": "Jetson AGX Xavier, 512-core Volta GPU",
                           "config": "CT9x7, 8-path SGM, LR check + median, incl. transfers"},
     }
+    del eng
+    torch.cuda.empty_cache()
+    if args.batch_reps > 0:
+        out["batched"] = batched_form(args, torch, dev, sgm, datagen)
+    if args.serve_seconds > 0:
+        out["served"] = served_form(args, torch, sgm, datagen)
     if args.cpu_frames > 0:
         out["cpu_baseline"] = cpu_baseline(pair, cfg, args.cpu_frames)
     print(json.dumps(out), flush=True)

@@ -167,10 +167,12 @@ typedef struct {
 
 typedef struct sgm_plan sgm_plan;
 
-/* Device workspace a plan needs for these pairs (0 on invalid arguments):
- * every pair's intermediates plus the plan's work-list tables. */
+/* Device workspace a plan needs for these pairs with this tuning table (the
+ * same table as sgm_batch_plan_create; it decides how the frames are grouped
+ * into launches): every pair's intermediates plus the plan's work-list
+ * tables.  0 on invalid arguments. */
 size_t sgm_batch_workspace_bytes(const sgm_pair* pairs, int32_t n,
-                                 const sgm_params* params);
+                                 const sgm_params* params, const char* tune_table);
 
 /*
  * Lays the intermediates out in `workspace` (256-byte aligned, at least
@@ -187,6 +189,10 @@ int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n,
                               const sgm_params* params, void* workspace,
                               size_t workspace_bytes, const char* tune_table,
                               sgm_plan** plan_out);
+
+/* Number of path-kernel lane-layout variants for this disparity range (the
+ * values a tuning table may give), >= 1; 0 for ndisp outside 1..256. */
+int32_t sgm_aggregate_variants(int32_t ndisp);
 
 /* Enqueues the captured batch on `stream` (one hipGraphLaunch).  Replays of
  * one plan must not overlap. */

@@ -189,14 +189,15 @@ size_t build_layout(const sgm_pair* pairs, int32_t n, const sgm_params* p, const
 
 extern "C" {
 
-size_t sgm_batch_workspace_bytes(const sgm_pair* pairs, int32_t n, const sgm_params* params) {
+size_t sgm_batch_workspace_bytes(const sgm_pair* pairs, int32_t n, const sgm_params* params,
+                                 const char* tune_table) {
     if (!pairs || n < 1 || !valid_params(params)) return 0;
     for (int i = 0; i < n; ++i)
         if (!valid_pair(pairs[i])) return 0;
     std::vector<Frame> frames;
     std::vector<Launch> launches;
     size_t tables_off;
-    return build_layout(pairs, n, params, nullptr, &frames, &launches, &tables_off);
+    return build_layout(pairs, n, params, tune_table, &frames, &launches, &tables_off);
 }
 
 int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n, const sgm_params* params,
@@ -293,6 +294,11 @@ int32_t sgm_batch_run(sgm_plan* plan, void* stream) {
 }
 
 int32_t sgm_batch_frames(const sgm_plan* plan) { return plan ? plan->nframes : 0; }
+
+int32_t sgm_aggregate_variants(int32_t ndisp) {
+    if (ndisp < 1 || ndisp > SGM_MAX_NDISP) return 0;
+    return path_variants(ndisp);
+}
 
 void sgm_batch_plan_destroy(sgm_plan* plan) {
     if (!plan) return;

@@ -98,10 +98,18 @@ def warp_right(rng: np.random.Generator, left: np.ndarray, disp: np.ndarray,
     if occlusion > 0:
         blob = np.zeros((height, width), bool)
         target = occlusion * width * height
-        while blob.sum() < target:
+        covered = 0
+        while covered < target:
             r = rng.uniform(3, max(4.0, 0.04 * min(width, height)))
             cx, cy = rng.uniform(0, width), rng.uniform(0, height)
-            blob |= (xs - cx) ** 2 + (ys - cy) ** 2 <= r * r
+            x0, x1 = max(0, int(cx - r)), min(width, int(cx + r) + 2)
+            y0, y1 = max(0, int(cy - r)), min(height, int(cy + r) + 2)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            sub = blob[y0:y1, x0:x1]
+            before = int(sub.sum())
+            sub |= (xs[y0:y1, x0:x1] - cx) ** 2 + (ys[y0:y1, x0:x1] - cy) ** 2 <= r * r
+            covered += int(sub.sum()) - before
         fill = _texture(rng, height, width)
         right[blob] = fill[blob]
         hit = np.zeros((height, width), bool)

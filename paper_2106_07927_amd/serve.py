@@ -1,0 +1,339 @@
+"""Served form of the path: continuous batching of frames from several
+simulated camera streams on one GPU.
+
+* Requests arrive per stream (Poisson traces from datagen.poisson_arrivals).
+* Each stream owns slots: resident device buffer sets (inputs, every
+  intermediate of the four ABI calls, the disparity output).  A slot is
+  allocated the first time the stream needs one and then reused for every
+  later frame of that stream; slots of all streams together stay under an
+  HBM budget; when a stream needs a slot that does not fit, an idle slot of
+  another stream is released (least recently used first).  A frame is
+  admitted as soon as one of its stream's slots is idle (or a new one fits
+  the budget) and a HIP stream of the pool is free,
+  so frames that arrive while others run start at once and overlap with them
+  on the device.  Per stream, frames are admitted in arrival order.
+* Per frame: pinned H2D copy of the pair, the four ABI calls, D2H copy of
+  the disparity map, all on the slot's HIP stream; completion is an event.
+  Latency = time of the event (read against an event recorded at the start)
+  minus the arrival time.
+* The plain reference serves the same trace FIFO, one frame at a time on one
+  stream.
+
+The scheduling loop is independent of the device: GpuBackend runs it on the
+GPU, FakeBackend simulates service times on a virtual clock for CPU tests.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import datagen
+
+
+@dataclass
+class Request:
+    stream: int
+    seq: int
+    arrival: float           # seconds from the start of the trace
+    frame: int               # index into the stream's frame pool
+
+
+@dataclass
+class StreamSpec:
+    width: int
+    height: int
+    ndisp: int
+    seed: int
+
+
+@dataclass
+class Result:
+    request: Request
+    start: float             # admission time
+    done: float              # completion time
+    slot: int
+
+
+@dataclass
+class Stats:
+    served: int = 0
+    rejected: int = 0
+    deferred: int = 0        # admissions that had to wait for a slot or budget
+    evictions: int = 0       # idle slots released to admit another stream
+    peak_bytes: int = 0
+    results: List[Result] = field(default_factory=list)
+
+    def latencies_ms(self):
+        return np.array([(r.done - r.request.arrival) * 1e3 for r in self.results])
+
+    def summary(self, specs) -> dict:
+        lat = self.latencies_ms()
+        span = max((r.done for r in self.results), default=0.0)
+        des = sum(specs[r.request.stream].width * specs[r.request.stream].height *
+                  specs[r.request.stream].ndisp for r in self.results)
+        return {"frames": self.served, "rejected": self.rejected, "deferred": self.deferred,
+                "evictions": self.evictions,
+                "p50_ms": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
+                "p99_ms": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
+                "max_ms": round(float(lat.max()), 3) if len(lat) else None,
+                "frames_per_s": round(self.served / span, 1) if span > 0 else None,
+                "mdes": round(des / span / 1e6, 1) if span > 0 else None,
+                "peak_gib": round(self.peak_bytes / 2 ** 30, 3)}
+
+
+def make_trace(specs, rate_hz: float, duration_s: float, frames_per_stream: int, seed: int):
+    """Merged, time-ordered Poisson arrivals of every stream."""
+    reqs = []
+    for s in range(len(specs)):
+        for k, t in enumerate(datagen.poisson_arrivals(rate_hz, duration_s, seed * 100 + s)):
+            reqs.append(Request(s, k, float(t), k % frames_per_stream))
+    reqs.sort(key=lambda r: (r.arrival, r.stream))
+    return reqs
+
+
+def slot_bytes(spec: StreamSpec, npaths: int, p2: int) -> int:
+    """Device bytes of one slot: inputs, census x2, cost, path slices, S_bar,
+    selection scratch, disparity maps (the buffers of one StereoSGM)."""
+    n = spec.width * spec.height
+    nd = spec.ndisp
+    slices = npaths * ((n * nd + 255) // 256 * 256) * (1 if p2 <= 255 else 2)
+    return 2 * n + 16 * n + n * nd + slices + 2 * n * nd + 6 * n + 4 * n
+
+
+class Server:
+    """Continuous-batching scheduler over a backend (see module docstring)."""
+
+    def __init__(self, specs: List[StreamSpec], backend, budget_bytes: int, hip_streams: int = 8,
+                 max_slots_per_stream: int = 2, npaths: int = 8, p2: int = 120):
+        self.specs = specs
+        self.backend = backend
+        self.budget = budget_bytes
+        self.hip_streams = hip_streams
+        self.max_slots = max_slots_per_stream
+        self.sizes = [slot_bytes(s, npaths, p2) for s in specs]
+        self.slots: Dict[int, List[dict]] = collections.defaultdict(list)
+        self.used_bytes = 0
+        self.evictions = 0
+        self._tick = 0
+
+    def _evict_for(self, need: int) -> bool:
+        """Releases idle slots, least recently used first, until `need` more
+        bytes fit; False if the idle slots are not enough."""
+        idle = sorted(((slot["last"], s, slot) for s, lst in self.slots.items() for slot in lst
+                       if slot["job"] is None), key=lambda t: t[0])
+        free = self.budget - self.used_bytes
+        if free + sum(self.sizes[s] for _, s, _ in idle) < need:
+            return False
+        for _, s, slot in idle:
+            if free >= need:
+                break
+            self.slots[s].remove(slot)
+            self.backend.free_slot(slot["handle"])
+            self.used_bytes -= self.sizes[s]
+            free += self.sizes[s]
+            self.evictions += 1
+        return True
+
+    def _free_slot(self, s: int) -> Optional[dict]:
+        self._tick += 1
+        for slot in self.slots[s]:
+            if slot["job"] is None:
+                slot["last"] = self._tick
+                return slot
+        if len(self.slots[s]) >= self.max_slots:
+            return None
+        if self.used_bytes + self.sizes[s] > self.budget:
+            if self.slots[s] or not self._evict_for(self.sizes[s]):
+                return None          # only a stream with no slot may evict others
+        slot = {"id": len(self.slots[s]), "handle": self.backend.alloc_slot(s), "job": None,
+                "last": self._tick}
+        self.slots[s].append(slot)
+        self.used_bytes += self.sizes[s]
+        return slot
+
+    def run(self, trace: List[Request], keep=None) -> Stats:
+        """Serves the trace; `keep(request)` says whether to copy a result to
+        the host for checking (the backend keeps it in result_of)."""
+        stats = Stats()
+        for s, size in enumerate(self.sizes):
+            if size > self.budget:
+                stats.rejected += sum(1 for r in trace if r.stream == s)
+        trace = [r for r in trace if self.sizes[r.stream] <= self.budget]
+        pending = collections.defaultdict(collections.deque)
+        inflight = []
+        waited = set()
+        i = 0
+        self.backend.start()
+        while i < len(trace) or inflight or any(pending.values()):
+            now = self.backend.now()
+            while i < len(trace) and trace[i].arrival <= now:
+                pending[trace[i].stream].append(trace[i])
+                i += 1
+            # completions free their slot
+            still = []
+            for job in inflight:
+                t_done = self.backend.done(job["handle"])
+                if t_done is not None:
+                    job["slot"]["job"] = None
+                    stats.results.append(Result(job["req"], job["start"], t_done, job["slot"]["id"]))
+                    stats.served += 1
+                else:
+                    still.append(job)
+            inflight = still
+            # admission: oldest waiting head first, per-stream FIFO
+            heads = sorted((q[0].arrival, s) for s, q in pending.items() if q)
+            for _, s in heads:
+                if len(inflight) >= self.hip_streams:
+                    break
+                slot = self._free_slot(s)
+                req = pending[s][0]
+                if slot is None:
+                    if (req.stream, req.seq) not in waited:
+                        waited.add((req.stream, req.seq))
+                        stats.deferred += 1
+                    continue
+                pending[s].popleft()
+                handle = self.backend.submit(s, slot["handle"], req, keep(req) if keep else False)
+                slot["job"] = handle
+                inflight.append({"req": req, "slot": slot, "handle": handle, "start": now})
+                stats.peak_bytes = max(stats.peak_bytes, self.used_bytes)
+            next_arrival = trace[i].arrival if i < len(trace) else None
+            if next_arrival is not None and not inflight and not any(pending.values()):
+                self.backend.wait_until(next_arrival)
+            else:
+                self.backend.idle(next_arrival)
+        stats.evictions = self.evictions
+        return stats
+
+
+class FakeBackend:
+    """Virtual clock; a frame takes N*D / rate seconds, frames overlap
+    freely (CPU tests of the scheduling logic)."""
+
+    def __init__(self, specs, mdes_per_s: float = 1e5):
+        self.specs = specs
+        self.rate = mdes_per_s * 1e6
+        self.t = 0.0
+        self.live = {}
+        self.result_of = {}
+        self.submitted = []
+
+    def start(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def alloc_slot(self, s):
+        self.allocs = getattr(self, "allocs", 0) + 1
+        return ("slot", s)
+
+    def free_slot(self, handle):
+        self.frees = getattr(self, "frees", 0) + 1
+
+    def submit(self, s, slot, req, keep):
+        sp = self.specs[s]
+        handle = object()
+        self.live[handle] = self.t + sp.width * sp.height * sp.ndisp / self.rate
+        self.submitted.append((self.t, req))
+        return handle
+
+    def done(self, handle):
+        t = self.live[handle]
+        return t if t <= self.t else None
+
+    def idle(self, next_arrival=None):
+        pending = [t for t in self.live.values() if t > self.t]
+        if next_arrival is not None and next_arrival > self.t:
+            pending.append(next_arrival)
+        self.t = min(pending) if pending else self.t + 1e-4
+
+    def wait_until(self, t):
+        self.t = max(self.t, t)
+
+
+class GpuBackend:
+    """Slots are StereoSGM buffer sets with their own device inputs; frames
+    run on a pool of HIP streams (default priority)."""
+
+    def __init__(self, specs, params, frames_per_stream: int = 4, device="cuda", occlusion=0.05):
+        import torch
+
+        from . import sgm
+        self.torch, self.sgm = torch, sgm
+        self.specs, self.params, self.device = specs, params, torch.device(device)
+        self.pool = []      # pinned host frames per stream
+        for s in specs:
+            frames = []
+            for k in range(frames_per_stream):
+                pair = datagen.make_pair(s.width, s.height, s.ndisp, s.seed * 10 + k, (8, 16), occlusion)
+                frames.append((torch.from_numpy(pair["left"]).pin_memory(),
+                               torch.from_numpy(pair["right"]).pin_memory()))
+            self.pool.append(frames)
+        self.result_of = {}
+        self.t0_event = None
+        self.t0 = 0.0
+
+    def start(self):
+        torch = self.torch
+        torch.cuda.synchronize()
+        self.t0_event = torch.cuda.Event(enable_timing=True)
+        self.t0 = time.perf_counter()
+        self.t0_event.record()
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def alloc_slot(self, s):
+        torch, sgm = self.torch, self.sgm
+        sp = self.specs[s]
+        prm = sgm.Params(**{**self.params.__dict__, "ndisp": sp.ndisp})
+        return {"eng": sgm.StereoSGM(sp.width, sp.height, prm, device=self.device),
+                "left": torch.empty((sp.height, sp.width), dtype=torch.uint8, device=self.device),
+                "right": torch.empty((sp.height, sp.width), dtype=torch.uint8, device=self.device),
+                "out": torch.empty((sp.height, sp.width), dtype=torch.uint16).pin_memory(),
+                "stream": torch.cuda.Stream(device=self.device)}
+
+    def submit(self, s, slot, req, keep):
+        torch = self.torch
+        hl, hr = self.pool[s][req.frame]
+        st = slot["stream"]
+        with torch.cuda.stream(st):
+            slot["left"].copy_(hl, non_blocking=True)
+            slot["right"].copy_(hr, non_blocking=True)
+            slot["eng"].run(slot["left"], slot["right"], stream=st)
+            slot["out"].copy_(slot["eng"].disp, non_blocking=True)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(st)
+        return {"event": ev, "slot": slot, "req": req, "keep": keep}
+
+    def done(self, handle):
+        ev = handle["event"]
+        if not ev.query():
+            return None
+        if handle["keep"]:
+            r = handle["req"]
+            self.result_of[(r.stream, r.seq)] = handle["slot"]["out"].numpy().copy()
+        return self.t0_event.elapsed_time(ev) * 1e-3
+
+    def free_slot(self, handle):
+        handle.clear()       # the caching allocator keeps the memory for the next slot
+
+    def idle(self, next_arrival=None):
+        time.sleep(5e-5)
+
+    def wait_until(self, t):
+        dt = t - self.now()
+        if dt > 0:
+            time.sleep(min(dt, 0.01))
+
+
+def serve_plain(trace, specs, backend) -> Stats:
+    """FIFO reference: one frame at a time, in arrival order, one stream."""
+    srv = Server(specs, backend, budget_bytes=1 << 62, hip_streams=1, max_slots_per_stream=1)
+    return srv.run(trace)

@@ -30,7 +30,8 @@ SGM_ERR_WORKSPACE = -5
 
 EXPORTS = ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_aggregate_work_bytes", "sgm_wta_lrc",
            "sgm_wta_lrc_work_elems", "sgm_batch_workspace_bytes", "sgm_batch_plan_create",
-           "sgm_batch_run", "sgm_batch_frames", "sgm_batch_plan_destroy", "sgm_status_string",
+           "sgm_batch_run", "sgm_batch_frames", "sgm_batch_plan_destroy", "sgm_aggregate_variants",
+           "sgm_status_string",
            "sgm_last_hip_error", "sgm_abi_version")
 
 
@@ -77,7 +78,7 @@ def load_library(path: str = LIB_PATH):
     lib.sgm_wta_lrc_work_elems.argtypes = [I32, I32]
     lib.sgm_wta_lrc_work_elems.restype = ctypes.c_size_t
     PP = ctypes.POINTER(SgmPair)
-    lib.sgm_batch_workspace_bytes.argtypes = [PP, I32, ctypes.POINTER(SgmParams)]
+    lib.sgm_batch_workspace_bytes.argtypes = [PP, I32, ctypes.POINTER(SgmParams), ctypes.c_char_p]
     lib.sgm_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.sgm_batch_plan_create.argtypes = [PP, I32, ctypes.POINTER(SgmParams), P, ctypes.c_size_t,
                                           ctypes.c_char_p, ctypes.POINTER(P)]
@@ -88,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     lib.sgm_batch_frames.restype = I32
     lib.sgm_batch_plan_destroy.argtypes = [P]
     lib.sgm_batch_plan_destroy.restype = None
+    lib.sgm_aggregate_variants.argtypes = [I32]
+    lib.sgm_aggregate_variants.restype = I32
     lib.sgm_status_string.argtypes = [I32]
     lib.sgm_status_string.restype = ctypes.c_char_p
     lib.sgm_last_hip_error.argtypes = []
@@ -296,14 +299,14 @@ class BatchPlan:
                                _ptr(dr).value if dr is not None else None)
         self._pairs = pairs
         prm = _params_struct(params)
-        need = int(lib.sgm_batch_workspace_bytes(pairs, n, ctypes.byref(prm)))
+        table = tune_table.encode() if tune_table else None
+        need = int(lib.sgm_batch_workspace_bytes(pairs, n, ctypes.byref(prm), table))
         if need == 0:
             raise ValueError("invalid batch (sizes, disparity ranges or parameters)")
         self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
         base = self.workspace.data_ptr()
         offset = (-base) % 256
         handle = ctypes.c_void_p()
-        table = tune_table.encode() if tune_table else None
         _check(lib.sgm_batch_plan_create(pairs, n, ctypes.byref(prm),
                                          ctypes.c_void_p(base + offset), need, table,
                                          ctypes.byref(handle)))

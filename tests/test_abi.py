@@ -122,17 +122,20 @@ def test_batch_validation(lib):
     pairs = (sgm.SgmPair * 2)()
     pairs[0] = sgm.SgmPair(FAKE, FAKE, 64, 48, 64, 64, FAKE, None)
     pairs[1] = sgm.SgmPair(FAKE, FAKE, 32, 16, 40, 16, FAKE, FAKE)
-    need = lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(prm))
+    need = lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(prm), None)
     # two frames of intermediates (census x2, cost, slices, agg, keys, D^L) plus tables
     n0, n1 = 64 * 48, 32 * 16
     lower = sum(8 * 2 * n + n * nd + 8 * n * nd + 2 * n * nd + 4 * n + 2 * n
                 for n, nd in ((n0, 64), (n1, 16)))
     assert need >= lower
-    assert lib.sgm_batch_workspace_bytes(pairs, 0, ctypes.byref(prm)) == 0
+    # a tuning table that splits the path launches needs more table space
+    split = lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(prm), b'{"64x48x64": 1}')
+    assert split >= need
+    assert lib.sgm_batch_workspace_bytes(pairs, 0, ctypes.byref(prm), None) == 0
     bad = sgm.SgmParams(7, 9, 8, 10, 120, 1, 1)                      # window
-    assert lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(bad)) == 0
+    assert lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(bad), None) == 0
     bad = sgm.SgmParams(9, 7, 8, 121, 120, 1, 1)                     # p1 > p2
-    assert lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(bad)) == 0
+    assert lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(bad), None) == 0
     handle = ctypes.c_void_p()
     pairs[1].pitch_bytes = 31                                        # pitch < width
     assert lib.sgm_batch_plan_create(pairs, 2, ctypes.byref(prm), P(FAKE), need, None,

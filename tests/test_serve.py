@@ -1,0 +1,75 @@
+"""Serving scheduler on the CPU (virtual clock, simulated service times):
+every request is served once, per-stream FIFO admission, the HBM budget is
+never exceeded, small budgets defer and evict instead of deadlocking,
+oversized streams are rejected, and the plain reference never overlaps."""
+import numpy as np
+
+from paper_2106_07927_amd import serve
+from paper_2106_07927_amd.serve import FakeBackend, Server, StreamSpec
+
+
+def specs():
+    return [StreamSpec(640, 512, 128, 1), StreamSpec(1242, 375, 128, 2),
+            StreamSpec(1920, 1080, 256, 3), StreamSpec(640, 512, 256, 4)]
+
+
+def run(budget, hip_streams=8, duration=2.0, rate=30.0, mdes=1e5):
+    sp = specs()
+    trace = serve.make_trace(sp, rate, duration, 4, seed=5)
+    be = FakeBackend(sp, mdes_per_s=mdes)
+    srv = Server(sp, be, budget_bytes=budget, hip_streams=hip_streams)
+    return sp, trace, be, srv, srv.run(trace)
+
+
+def test_every_request_served_once_and_fifo_per_stream():
+    sp, trace, be, srv, st = run(budget=64 << 30)
+    assert st.served == len(trace) and st.rejected == 0
+    seen = {(r.request.stream, r.request.seq) for r in st.results}
+    assert len(seen) == len(trace)
+    for s in range(len(sp)):
+        seqs = [req.seq for (_, req) in be.submitted if req.stream == s]
+        assert seqs == sorted(seqs)
+    lat = st.latencies_ms()
+    service = {s: sp[s].width * sp[s].height * sp[s].ndisp / 1e11 * 1e3 for s in range(len(sp))}
+    for r, l in zip(st.results, lat):
+        assert l >= service[r.request.stream] - 1e-9
+    assert st.peak_bytes <= 64 << 30
+
+
+def test_budget_is_respected_with_waits_and_evictions():
+    sizes = [serve.slot_bytes(s, 8, 120) for s in specs()]
+    budget = max(sizes) + min(sizes)               # room for about two slots
+    sp, trace, be, srv, st = run(budget=budget, mdes=2e4)
+    assert st.served == len(trace)
+    assert st.peak_bytes <= budget
+    assert st.deferred > 0 and st.evictions > 0
+    assert srv.used_bytes <= budget
+    live = sum(srv.sizes[s] for s, lst in srv.slots.items() for _ in lst)
+    assert live == srv.used_bytes and be.allocs - be.frees == sum(len(v) for v in srv.slots.values())
+
+
+def test_oversized_stream_is_rejected():
+    sizes = [serve.slot_bytes(s, 8, 120) for s in specs()]
+    budget = sorted(sizes)[-2]                      # the largest stream never fits
+    sp, trace, be, srv, st = run(budget=budget)
+    big = int(np.argmax(sizes))
+    assert st.rejected == sum(1 for r in trace if r.stream == big)
+    assert st.served == len(trace) - st.rejected
+
+
+def test_plain_reference_serves_one_at_a_time():
+    sp = specs()
+    trace = serve.make_trace(sp, 30.0, 1.0, 4, seed=9)
+    st = serve.serve_plain(trace, sp, FakeBackend(sp, mdes_per_s=5e4))
+    spans = sorted((r.start, r.done) for r in st.results)
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert b0 >= a1 - 1e-12
+    assert st.served == len(trace)
+
+
+def test_continuous_batching_beats_fifo_on_latency():
+    sp = specs()
+    trace = serve.make_trace(sp, 30.0, 2.0, 4, seed=11)
+    mix = Server(sp, FakeBackend(sp, mdes_per_s=3e4), budget_bytes=1 << 40).run(trace)
+    fifo = serve.serve_plain(trace, sp, FakeBackend(sp, mdes_per_s=3e4))
+    assert np.percentile(mix.latencies_ms(), 99) <= np.percentile(fifo.latencies_ms(), 99)
