@@ -7,11 +7,14 @@ One step = one pass of the whole path over one synthetic stereo pair whose
 images are already resident in HBM: census (left and right), Hamming cost,
 8-path aggregation, WTA + approximate D^R + LR check + 3x3 median.  The
 default workload is a 1242x375 pair, D = 128, census 9x7, P1 = 10, P2 = 120.
+The timed path is the streamlined one (aggregation fused with the selection,
+sgm_aggregate_select); the four-call path (sgm_aggregate + sgm_wta_lrc, same
+bits) is timed the same way and reported beside it.
 
 Prints ONE JSON line with the throughput in MDE/s (W * H * D / step time, the
-paper's Eq. mdes), FPS, the aggregation kernel's roofline fraction (timed
-with HIP events on the stream it runs on), and the CPU oracle timed on a
-bounded sample of the same workload.
+paper's Eq. mdes), FPS, the dominant unit's roofline fraction (timed with HIP
+events on the stream it runs on), the batched and served forms, and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -42,7 +45,52 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the served trace (0 skips the served form)")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the path, run a plain device copy of this many MiB five "
+                         "times (the known-size kernel that scales HBM counter readings)")
     return ap.parse_args()
+
+
+# HBM bytes per call at the 1242x375 / D=128 / 8-path frame, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs of this script (profiles/hbm_traffic_*), each
+# scaled by what the same counter reads for a plain copy of known size.  An
+# entry holds only for the kernel sources whose digest it names; for any other
+# sources the figure is reported as null.
+TRAFFIC = {}
+
+KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "wta_lrc.hip", "sgm_internal.h")
+
+
+def sources_digest():
+    import hashlib
+    hsh = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_07927_amd", "csrc", name), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()[:16]
+
+
+def traffic(unit, digest):
+    entry = TRAFFIC.get(unit)
+    if entry is None or entry["sources"] != digest:
+        return None
+    return entry["bytes"]
+
+
+def percentile(sorted_vals, q):
+    return sorted_vals[min(len(sorted_vals) - 1, int(q * len(sorted_vals)))]
+
+
+def copy_probe(torch, dev, mib):
+    """A plain elementwise copy of known size: reads and writes `mib` MiB per
+    launch.  Its FETCH_SIZE / WRITE_SIZE readings calibrate the counters."""
+    n = mib * 2 ** 20 // 4
+    src = torch.arange(n, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def batched_form(args, torch, dev, sgm, datagen):
@@ -159,49 +207,78 @@ def main():
                      p1=cfg["p1"], p2=cfg["p2"], lr_tolerance=cfg["lr_tolerance"],
                      median3x3=cfg["median3x3"])
     pair = datagen.config_pair(args.workload)
-    eng = sgm.StereoSGM(w, h, prm, device=dev)
     left = torch.from_numpy(pair["left"]).to(dev)
     right = torch.from_numpy(pair["right"]).to(dev)
     stream = torch.cuda.current_stream()
+    if args.copy_probe_mib > 0:
+        copy_probe(torch, dev, args.copy_probe_mib)
 
-    def step(ev=None):
-        sgm.sgm_census(left, prm.win_w, prm.win_h, out=eng.census_left)
-        sgm.sgm_census(right, prm.win_w, prm.win_h, out=eng.census_right)
-        if ev is not None:
-            ev[0].record(stream)
-        sgm.sgm_cost(eng.census_left, eng.census_right, nd, out=eng.cost)
-        if ev is not None:
-            ev[1].record(stream)
-        sgm.sgm_aggregate(eng.cost, npaths, prm.p1, prm.p2, out=eng.agg, work=eng.agg_work)
-        if ev is not None:
-            ev[2].record(stream)
-        sgm.sgm_wta_lrc(eng.agg, prm.lr_tolerance, prm.median3x3, out=eng.disp,
-                        out_right=eng.disp_right, work=eng.work)
+    def timed(fused):
+        """K steps of the whole path (after W warm-up steps); events on the
+        launch stream bracket every stage of every step."""
+        eng = sgm.StereoSGM(w, h, prm, device=dev, fused=fused)
+        names = ("census", "cost", "aggregate_select") if fused else \
+            ("census", "cost", "aggregate", "wta_lrc")
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+        def step(ev=None):
+            def mark(i):
+                if ev is not None:
+                    ev[i].record(stream)
+            mark(0)
+            sgm.sgm_census(left, prm.win_w, prm.win_h, out=eng.census_left)
+            sgm.sgm_census(right, prm.win_w, prm.win_h, out=eng.census_right)
+            mark(1)
+            sgm.sgm_cost(eng.census_left, eng.census_right, nd, out=eng.cost)
+            mark(2)
+            if fused:
+                sgm.sgm_aggregate_select(eng.cost, npaths, prm.p1, prm.p2, prm.lr_tolerance,
+                                         prm.median3x3, out=eng.disp, out_right=eng.disp_right,
+                                         work=eng.select_work)
+            else:
+                sgm.sgm_aggregate(eng.cost, npaths, prm.p1, prm.p2, out=eng.agg, work=eng.agg_work)
+                mark(3)
+                sgm.sgm_wta_lrc(eng.agg, prm.lr_tolerance, prm.median3x3, out=eng.disp,
+                                out_right=eng.disp_right, work=eng.work)
+            mark(len(names))
 
-    # timed region: K steps between two synchronisations; events bracket the
-    # aggregation call of every step on the stream it is launched on
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for i in range(args.steps):
-        step(evs[i])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    ms_step = total_ms / args.steps
-    agg_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
-    cost_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+               for _ in range(args.steps)]
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        for i in range(args.steps):
+            step(evs[i])
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        per_step = sorted(e[0].elapsed_time(e[-1]) for e in evs)
+        stages = {nm: sum(e[a].elapsed_time(e[a + 1]) for e in evs) / args.steps
+                  for a, nm in enumerate(names)}
+        return eng, step, {"ms_per_step": t_start.elapsed_time(t_end) / args.steps,
+                           "stages_ms": stages, "per_step": per_step}
 
     des = w * h * nd
+    four_eng, _, four = timed(False)
+    del four_eng
+    eng, step, main_t = timed(True)
+    ms_step = main_t["ms_per_step"]
     mdes = des / (ms_step * 1e-3) / 1e6
-    agg_bytes = (npaths + 2) * des            # R reads of the uint8 volume + one uint16 write
-    achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
+    per_step = main_t["per_step"]
+
+    # roofline of the dominant unit of the timed path: sgm_aggregate_select,
+    # whose algorithmic bytes are the cost volume streamed once per path plus
+    # the two disparity maps written
+    sel_ms = main_t["stages_ms"]["aggregate_select"]
+    sel_bytes = npaths * des + 4 * w * h
+    achieved = sel_bytes / (sel_ms * 1e-3) / 1e9
+    # the four-call form's sgm_aggregate: R reads of the uint8 volume + one
+    # uint16 write of S_bar
+    agg_ms = four["stages_ms"]["aggregate"]
+    agg_bytes = (npaths + 2) * des
+    agg_achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
 
     # PCIe-inclusive frame (context only): pinned H2D of the pair, path, D2H of D
     hl = torch.from_numpy(pair["left"]).pin_memory()
@@ -217,6 +294,7 @@ def main():
         hd.copy_(eng.disp, non_blocking=True)
     torch.cuda.synchronize()
     e2e_ms = (time.perf_counter() - t0) * 1e3 / e2e_n
+    digest = sources_digest()
 
     out = {
         "metric": METRIC,
@@ -237,11 +315,26 @@ def main():
                                f"median {int(cfg['median3x3'])}",
                    "width": w, "height": h, "ndisp": nd, "npaths": npaths, "frames_per_step": 1},
         "fps": round(1000.0 / ms_step, 1),
-        "stages_ms": {"aggregate": round(agg_ms, 5), "cost": round(cost_ms, 5)},
+        "stages_ms": {k: round(v, 5) for k, v in main_t["stages_ms"].items()},
+        "step_ms_p50": round(percentile(per_step, 0.5), 5),
+        "step_ms_p99": round(percentile(per_step, 0.99), 5),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "sgm_aggregate (paths_kernel + merge_u8_kernel)",
-                     "algorithmic_bytes": agg_bytes},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic("sgm_aggregate_select", digest),
+                     "kernel": "sgm_aggregate_select (paths_kernel + fill_u32_kernel + "
+                               "select_fused_kernel + check_median_kernel)",
+                     "algorithmic_bytes": sel_bytes},
+        "four_call": {"ms_per_step": round(four["ms_per_step"], 5),
+                      "value": round(des / (four["ms_per_step"] * 1e-3) / 1e6, 1),
+                      "stages_ms": {k: round(v, 5) for k, v in four["stages_ms"].items()},
+                      "step_ms_p50": round(percentile(four["per_step"], 0.5), 5),
+                      "step_ms_p99": round(percentile(four["per_step"], 0.99), 5),
+                      "roofline_sgm_aggregate": {
+                          "bound": "hbm", "achieved": round(agg_achieved, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(agg_achieved / HBM_PEAK_GBS, 4),
+                          "traffic": traffic("sgm_aggregate", digest),
+                          "kernel": "sgm_aggregate (paths_kernel + merge_kernel)",
+                          "algorithmic_bytes": agg_bytes}},
         "e2e_pcie_ms_per_frame": round(e2e_ms, 4),
         "paper_context": {"value": 644.9, "unit": "MDE/s",
                           "hardware": "Jetson AGX Xavier, 512-core Volta GPU",

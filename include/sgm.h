@@ -139,6 +139,32 @@ int32_t sgm_wta_lrc(const uint16_t* agg, int32_t width, int32_t height,
 /* Number of uint16 elements sgm_wta_lrc needs in `work` (0 on bad sizes). */
 size_t sgm_wta_lrc_work_elems(int32_t width, int32_t height);
 
+/*
+ * Streamlined aggregation: sgm_aggregate followed by sgm_wta_lrc in one call
+ * whose path sum S_bar never reaches device memory.  The paper points to
+ * fusing the last aggregation step with the disparity selection as a known
+ * speed-up for GPU SGM (Sec. 4.2); here the path sum of Eq. (sgm_path_aggr)
+ * is formed on chip inside the selection pass.  disp_out and disp_right_out
+ * are bit-identical to those two calls with the same arguments.
+ * The fused form applies when ndisp % 16 == 0 and p2 <= 255; other valid
+ * arguments run the two unfused calls on the same workspace.
+ *   cost, npaths, p1, p2          as for sgm_aggregate
+ *   lr_tolerance, median3x3,
+ *   disp_out, disp_right_out      as for sgm_wta_lrc
+ *   work       device scratch of sgm_aggregate_select_work_bytes(...) bytes,
+ *              256-byte aligned; contents on return are unspecified
+ * Errors: SGM_ERR_ARG, SGM_ERR_WORKSPACE, SGM_ERR_ALIGN, SGM_ERR_HIP.
+ */
+int32_t sgm_aggregate_select(const uint8_t* cost, int32_t width, int32_t height,
+                             int32_t ndisp, int32_t npaths, int32_t p1, int32_t p2,
+                             int32_t lr_tolerance, int32_t median3x3,
+                             uint16_t* disp_out, uint16_t* disp_right_out,
+                             void* work, size_t work_bytes, void* stream);
+
+/* Bytes of `work` that sgm_aggregate_select needs (0 on invalid arguments). */
+size_t sgm_aggregate_select_work_bytes(int32_t width, int32_t height, int32_t ndisp,
+                                       int32_t npaths, int32_t p2);
+
 /* ---------------------------------------------------------------------------
  * Batched form: many rectified pairs, each with its own size and disparity
  * range, run as one hipGraph launch.  Each pair's outputs are bit-identical

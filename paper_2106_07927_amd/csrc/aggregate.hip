@@ -367,51 +367,28 @@ __global__ __launch_bounds__(kThreads) void paths_batch_kernel(WorkList wl) {
 }
 
 // S_bar = R * C + sum_r A_r over uint8 penalty slices, for the kMergeChunk
-// elements of block lb; each thread sums 16 consecutive elements.  Bytes are
-// split into even/odd 16-bit lanes so that plain 32-bit adds accumulate two
-// sums per register without carries.
+// elements of block lb; each thread sums 16 consecutive elements.
+template <int NP, bool PAIR>
 __device__ __forceinline__ void merge_u8_block(const Frame& f, int lb) {
     const size_t n = (size_t)f.width * f.height * f.ndisp;
     const size_t e0 = (size_t)lb * kMergeChunk + (size_t)threadIdx.x * 16;
     const uint8_t* cost = f.cost;
     const uint8_t* slices = f.slices;
     uint16_t* agg = f.agg;
-    const uint32_t npaths = (uint32_t)f.npaths;
     if (e0 + 16 <= n) {
         const size_t i = e0 / 16;
         const uint4 c = reinterpret_cast<const uint4*>(cost)[i];
-        const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
-        uint32_t ev[4], od[4];
+        uint4 a[NP];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            ev[q] = (cw[q] & 0x00FF00FFu) * npaths;
-            od[q] = ((cw[q] >> 8) & 0x00FF00FFu) * npaths;
-        }
-        for (uint32_t r = 0; r < npaths; ++r) {
-            const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * f.slice_stride)[i];
-            const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                ev[q] += aw[q] & 0x00FF00FFu;
-                od[q] += (aw[q] >> 8) & 0x00FF00FFu;
-            }
-        }
-        // interleave back: element order e0 o0 e1 o1 per 32-bit source word
-        uint4 lo, hi;
-        lo.x = __builtin_amdgcn_perm(od[0], ev[0], 0x05040100u);
-        lo.y = __builtin_amdgcn_perm(od[0], ev[0], 0x07060302u);
-        lo.z = __builtin_amdgcn_perm(od[1], ev[1], 0x05040100u);
-        lo.w = __builtin_amdgcn_perm(od[1], ev[1], 0x07060302u);
-        hi.x = __builtin_amdgcn_perm(od[2], ev[2], 0x05040100u);
-        hi.y = __builtin_amdgcn_perm(od[2], ev[2], 0x07060302u);
-        hi.z = __builtin_amdgcn_perm(od[3], ev[3], 0x05040100u);
-        hi.w = __builtin_amdgcn_perm(od[3], ev[3], 0x07060302u);
-        reinterpret_cast<uint4*>(agg)[2 * i] = lo;
-        reinterpret_cast<uint4*>(agg)[2 * i + 1] = hi;
+        for (int r = 0; r < NP; ++r) a[r] = reinterpret_cast<const uint4*>(slices + (size_t)r * f.slice_stride)[i];
+        uint32_t s[8];
+        merge16<NP, PAIR>(c, a, s);
+        reinterpret_cast<uint4*>(agg)[2 * i] = make_uint4(s[0], s[1], s[2], s[3]);
+        reinterpret_cast<uint4*>(agg)[2 * i + 1] = make_uint4(s[4], s[5], s[6], s[7]);
     } else {
         for (size_t e = e0; e < n && e < e0 + 16; ++e) {
-            uint32_t s = (uint32_t)cost[e] * npaths;
-            for (uint32_t r = 0; r < npaths; ++r) s += slices[(size_t)r * f.slice_stride + e];
+            uint32_t s = (uint32_t)cost[e] * NP;
+            for (int r = 0; r < NP; ++r) s += slices[(size_t)r * f.slice_stride + e];
             agg[e] = (uint16_t)s;
         }
     }
@@ -446,19 +423,30 @@ __device__ __forceinline__ void merge_u16_block(const Frame& f, int lb) {
     }
 }
 
-template <bool U8>
-__global__ __launch_bounds__(256) void merge_kernel(Frame f) {
-    if constexpr (U8) merge_u8_block(f, blockIdx.x);
-    else merge_u16_block(f, blockIdx.x);
+// MODE: 0 = uint16 slices, 1 / 2 = uint8 slices of 4 / 8 paths, 3 / 4 = the
+// same with P2 <= 127 (bytewise pair sums)
+template <int MODE>
+__device__ __forceinline__ void merge_block(const Frame& f, int lb) {
+    if constexpr (MODE == 0) merge_u16_block(f, lb);
+    else merge_u8_block<(MODE == 1 || MODE == 3) ? 4 : 8, (MODE >= 3)>(f, lb);
 }
 
-template <bool U8>
+template <int MODE>
+__global__ __launch_bounds__(256) void merge_kernel(Frame f) {
+    merge_block<MODE>(f, blockIdx.x);
+}
+
+template <int MODE>
 __global__ __launch_bounds__(256) void merge_batch_kernel(WorkList wl) {
     for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
         const int fi = find_frame(wl, b);
-        if constexpr (U8) merge_u8_block(wl.frames[fi], b - wl.starts[fi]);
-        else merge_u16_block(wl.frames[fi], b - wl.starts[fi]);
+        merge_block<MODE>(wl.frames[fi], b - wl.starts[fi]);
     }
+}
+
+int merge_mode(int npaths, int p2) {
+    if (p2 > 255) return 0;
+    return (npaths == 4 ? 1 : 2) + (p2 <= 127 ? 2 : 0);
 }
 
 // Path-kernel launch for one lane layout; `batch` selects the persistent
@@ -558,15 +546,23 @@ size_t aggregate_work_bytes(int width, int height, int ndisp, int npaths, int p2
     return (size_t)npaths * aggregate_slice_elems(width, height, ndisp) * (p2 <= 255 ? 1 : 2);
 }
 
-hipError_t launch_aggregate(const Frame& f, hipStream_t stream) {
+hipError_t launch_paths(const Frame& f, hipStream_t stream) {
     const int variant = (f.variant >= 0 && f.variant < path_variants(f.ndisp)) ? f.variant : 0;
-    const bool u8 = f.p2 <= 255;
     const int nb = path_blocks(f.width, f.height, f.ndisp, f.npaths, variant);
-    hipError_t e = launch_paths_any(&f, nullptr, f.ndisp, variant, u8, nb, stream);
+    return launch_paths_any(&f, nullptr, f.ndisp, variant, f.p2 <= 255, nb, stream);
+}
+
+hipError_t launch_aggregate(const Frame& f, hipStream_t stream) {
+    hipError_t e = launch_paths(f, stream);
     if (e != hipSuccess) return e;
     const int mb = merge_blocks((size_t)f.width * f.height * f.ndisp);
-    if (u8) merge_kernel<true><<<mb, 256, 0, stream>>>(f);
-    else merge_kernel<false><<<mb, 256, 0, stream>>>(f);
+    switch (merge_mode(f.npaths, f.p2)) {
+        case 0: merge_kernel<0><<<mb, 256, 0, stream>>>(f); break;
+        case 1: merge_kernel<1><<<mb, 256, 0, stream>>>(f); break;
+        case 2: merge_kernel<2><<<mb, 256, 0, stream>>>(f); break;
+        case 3: merge_kernel<3><<<mb, 256, 0, stream>>>(f); break;
+        default: merge_kernel<4><<<mb, 256, 0, stream>>>(f); break;
+    }
     return hipGetLastError();
 }
 
@@ -577,10 +573,15 @@ hipError_t launch_paths_batch(const WorkList& wl, int ndisp, int npaths, int p2,
     return launch_paths_any(nullptr, &wl, ndisp, variant, p2 <= 255, wl.total, stream);
 }
 
-hipError_t launch_merge_batch(const WorkList& wl, bool u8, hipStream_t stream) {
+hipError_t launch_merge_batch(const WorkList& wl, int npaths, int p2, hipStream_t stream) {
     const int grid = persistent_grid(wl.total);
-    if (u8) merge_batch_kernel<true><<<grid, 256, 0, stream>>>(wl);
-    else merge_batch_kernel<false><<<grid, 256, 0, stream>>>(wl);
+    switch (merge_mode(npaths, p2)) {
+        case 0: merge_batch_kernel<0><<<grid, 256, 0, stream>>>(wl); break;
+        case 1: merge_batch_kernel<1><<<grid, 256, 0, stream>>>(wl); break;
+        case 2: merge_batch_kernel<2><<<grid, 256, 0, stream>>>(wl); break;
+        case 3: merge_batch_kernel<3><<<grid, 256, 0, stream>>>(wl); break;
+        default: merge_batch_kernel<4><<<grid, 256, 0, stream>>>(wl); break;
+    }
     return hipGetLastError();
 }
 

@@ -7,8 +7,11 @@
 // the tuning table), writes one device work list per stage and group, and
 // captures the whole sequence into a hipGraph:
 //     census (all frames, both images) -> cost (per D) -> paths (per D and
-//     variant) -> merge (all) -> D^R key fill (all) -> select (per D) ->
-//     LR check + median (all)
+//     variant) -> D^R key fill (all) -> path sum fused with the selection
+//     (per D) -> LR check + median (all)
+// Frames whose disparity range or penalties rule out the fused selection
+// (D % 16 != 0, P2 > 255) take merge (S_bar in the workspace) and the plain
+// selection instead.
 // Every stage is one persistent launch that walks its work list of
 // (frame, block) items; the blocks of a frame are exactly those of the
 // single-frame call, so each frame's results are bit-identical to it.
@@ -48,7 +51,7 @@ FrameLayout frame_layout(int w, int h, int nd, int npaths, int p2) {
     l.census = align256(8 * n);
     l.cost = align256(n * nd);
     l.slices = align256(aggregate_work_bytes(w, h, nd, npaths, p2));
-    l.agg = align256(2 * n * nd);
+    l.agg = fused_select_supported(nd, npaths, p2) ? 0 : align256(2 * n * nd);
     l.keys = align256(4 * n);
     l.dl = align256(2 * n);
     l.total = 2 * l.census + l.cost + l.slices + l.agg + l.keys + l.dl;
@@ -67,7 +70,7 @@ int tuned_variant(const char* table, int w, int h, int nd) {
     return (int)strtol(p + 1, nullptr, 10);
 }
 
-enum Stage { kCensus, kCost, kPaths, kMerge, kFill, kSelect, kMedian, kStages };
+enum Stage { kCensus, kCost, kPaths, kMerge, kFill, kSelect, kFused, kMedian, kStages };
 
 int stage_blocks(Stage st, const Frame& f) {
     const size_t n = (size_t)f.width * f.height;
@@ -77,7 +80,8 @@ int stage_blocks(Stage st, const Frame& f) {
         case kPaths: return path_blocks(f.width, f.height, f.ndisp, f.npaths, f.variant);
         case kMerge: return merge_blocks(n * f.ndisp);
         case kFill: return fill_blocks(n);
-        case kSelect: return select_blocks_x(f.width) * f.height;
+        case kSelect:
+        case kFused: return select_blocks_x(f.width) * f.height;
         case kMedian: return median_blocks(f.width, f.height);
         default: return 0;
     }
@@ -162,16 +166,21 @@ size_t build_layout(const sgm_pair* pairs, int32_t n, const sgm_params* p, const
     for (int i = 0; i < n; ++i) all[i] = i;
     std::map<int, std::vector<int>> by_d;
     std::map<std::pair<int, int>, std::vector<int>> by_dv;
+    std::vector<int> unfused;
     for (int i = 0; i < n; ++i) {
         by_d[(*frames)[i].ndisp].push_back(i);
         by_dv[{(*frames)[i].ndisp, (*frames)[i].variant}].push_back(i);
+        if (!fused_select_supported((*frames)[i].ndisp, p->npaths, p->p2)) unfused.push_back(i);
     }
     launches->push_back({kCensus, 0, 0, all});
     for (auto& kv : by_d) launches->push_back({kCost, kv.first, 0, kv.second});
     for (auto& kv : by_dv) launches->push_back({kPaths, kv.first.first, kv.first.second, kv.second});
-    launches->push_back({kMerge, 0, 0, all});
+    if (!unfused.empty()) launches->push_back({kMerge, 0, 0, unfused});
     launches->push_back({kFill, 0, 0, all});
-    for (auto& kv : by_d) launches->push_back({kSelect, kv.first, 0, kv.second});
+    for (auto& kv : by_d) {
+        const bool fused = fused_select_supported(kv.first, p->npaths, p->p2);
+        launches->push_back({fused ? kFused : kSelect, kv.first, 0, kv.second});
+    }
     launches->push_back({kMedian, 0, 0, all});
     // tables: one frame table per launch (frames of the group, in order) and
     // its block starts
@@ -222,7 +231,9 @@ int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n, const sgm_params
         f.census_right = reinterpret_cast<uint64_t*>(base + reinterpret_cast<uintptr_t>(f.census_right));
         f.cost = reinterpret_cast<uint8_t*>(base + reinterpret_cast<uintptr_t>(f.cost));
         f.slices = reinterpret_cast<uint8_t*>(base + reinterpret_cast<uintptr_t>(f.slices));
-        f.agg = reinterpret_cast<uint16_t*>(base + reinterpret_cast<uintptr_t>(f.agg));
+        f.agg = fused_select_supported(f.ndisp, f.npaths, f.p2)
+                    ? nullptr
+                    : reinterpret_cast<uint16_t*>(base + reinterpret_cast<uintptr_t>(f.agg));
         f.right_keys = reinterpret_cast<uint32_t*>(base + reinterpret_cast<uintptr_t>(f.right_keys));
         f.disp_left = reinterpret_cast<uint16_t*>(base + reinterpret_cast<uintptr_t>(f.disp_left));
     }
@@ -254,7 +265,6 @@ int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n, const sgm_params
     e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        const bool u8 = params->p2 <= 255;
         hipStream_t s = plan->capture_stream;
         for (const Launch& L : launches) {
             hipError_t le = hipSuccess;
@@ -262,9 +272,12 @@ int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n, const sgm_params
                 case kCensus: le = launch_census_batch(L.wl, params->win_w, params->win_h, s); break;
                 case kCost: le = launch_cost_batch(L.wl, L.ndisp, s); break;
                 case kPaths: le = launch_paths_batch(L.wl, L.ndisp, params->npaths, params->p2, L.variant, s); break;
-                case kMerge: le = launch_merge_batch(L.wl, u8, s); break;
+                case kMerge: le = launch_merge_batch(L.wl, params->npaths, params->p2, s); break;
                 case kFill: le = launch_fill_keys_batch(L.wl, s); break;
                 case kSelect: le = launch_select_batch(L.wl, L.ndisp, s); break;
+                case kFused:
+                    le = launch_select_fused_batch(L.wl, L.ndisp, params->npaths, params->p2, s);
+                    break;
                 case kMedian: le = launch_median_batch(L.wl, s); break;
                 default: break;
             }

@@ -41,11 +41,28 @@ int32_t hip_status(hipError_t e) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Workspace of sgm_aggregate_select: path slices, S_bar (only where the fused
+// selection does not apply), D^R keys, D^L.  Returns the total bytes.
+size_t select_layout(int32_t width, int32_t height, int32_t ndisp, int32_t npaths, int32_t p2,
+                     size_t* agg_off, size_t* keys_off, size_t* dl_off) {
+    const size_t n = (size_t)width * height;
+    size_t off = align256(sgm::aggregate_work_bytes(width, height, ndisp, npaths, p2));
+    *agg_off = off;
+    if (!sgm::fused_select_supported(ndisp, npaths, p2)) off += align256(2 * n * (size_t)ndisp);
+    *keys_off = off;
+    off += align256(4 * n);
+    *dl_off = off;
+    off += align256(2 * n);
+    return off;
+}
+
 }  // namespace
 
 extern "C" {
 
-int32_t sgm_abi_version(void) { return 2; }
+int32_t sgm_abi_version(void) { return 3; }
 
 const char* sgm_status_string(int32_t status) {
     switch (status) {
@@ -151,6 +168,53 @@ int32_t sgm_wta_lrc(const uint16_t* agg, int32_t width, int32_t height, int32_t 
     f.disp = disp_out;
     f.disp_right = disp_right_out;
     return hip_status(sgm::launch_wta_lrc(f, as_stream(stream)));
+}
+
+size_t sgm_aggregate_select_work_bytes(int32_t width, int32_t height, int32_t ndisp,
+                                       int32_t npaths, int32_t p2) {
+    if (bad_size(width, height) || bad_volume(width, height, ndisp) || bad_penalties(npaths, 0, p2))
+        return 0;
+    size_t a, k, d;
+    return select_layout(width, height, ndisp, npaths, p2, &a, &k, &d);
+}
+
+int32_t sgm_aggregate_select(const uint8_t* cost, int32_t width, int32_t height, int32_t ndisp,
+                             int32_t npaths, int32_t p1, int32_t p2, int32_t lr_tolerance,
+                             int32_t median3x3, uint16_t* disp_out, uint16_t* disp_right_out,
+                             void* work, size_t work_bytes, void* stream) {
+    if (!cost || !disp_out || bad_size(width, height)) return SGM_ERR_ARG;
+    if (bad_volume(width, height, ndisp) || bad_penalties(npaths, p1, p2)) return SGM_ERR_ARG;
+    if (median3x3 != 0 && median3x3 != 1) return SGM_ERR_ARG;
+    size_t agg_off, keys_off, dl_off;
+    const size_t need = select_layout(width, height, ndisp, npaths, p2, &agg_off, &keys_off, &dl_off);
+    if (!work || work_bytes < need) return SGM_ERR_WORKSPACE;
+    if (!aligned(cost, 16) || !aligned(work, 256) || !aligned(disp_out, 4) ||
+        (disp_right_out && !aligned(disp_right_out, 4)))
+        return SGM_ERR_ALIGN;
+    char* base = static_cast<char*>(work);
+    sgm::Frame f{};
+    f.width = width;
+    f.height = height;
+    f.ndisp = ndisp;
+    f.npaths = npaths;
+    f.p1 = p1;
+    f.p2 = p2;
+    f.lr_tolerance = lr_tolerance;
+    f.median3x3 = median3x3;
+    f.variant = 0;
+    f.cost = const_cast<uint8_t*>(cost);
+    f.slices = reinterpret_cast<uint8_t*>(base);
+    f.slice_stride = sgm::aggregate_slice_elems(width, height, ndisp);
+    f.right_keys = reinterpret_cast<uint32_t*>(base + keys_off);
+    f.disp_left = reinterpret_cast<uint16_t*>(base + dl_off);
+    f.disp = disp_out;
+    f.disp_right = disp_right_out;
+    const hipStream_t s = as_stream(stream);
+    if (sgm::fused_select_supported(ndisp, npaths, p2)) return hip_status(sgm::launch_aggregate_select(f, s));
+    f.agg = reinterpret_cast<uint16_t*>(base + agg_off);
+    const hipError_t e = sgm::launch_aggregate(f, s);
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(sgm::launch_wta_lrc(f, s));
 }
 
 }  // extern "C"

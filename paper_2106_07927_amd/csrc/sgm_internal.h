@@ -34,6 +34,50 @@ __device__ __forceinline__ uint32_t pk_shift_in(uint32_t a, uint32_t b) {
 __host__ __device__ __forceinline__ uint32_t pk_splat(uint32_t v16) { return v16 | (v16 << 16); }
 
 // ---------------------------------------------------------------------------
+// Path sum of 16 consecutive volume elements (Eq. sgm_path_aggr) from uint8
+// penalty slices: S = NP * C + sum_r A_r, with A_r = L_r - C in [0, P2].
+// Bytes are split into even / odd 16-bit lanes, so plain 32-bit adds carry
+// two sums per register with no carry between them (S <= NP * (255 + P2) <
+// 2^16).  With PAIR (P2 <= 127) two slices are first added bytewise: each
+// byte sum is at most 254, so no carry crosses a byte either.  `out` holds the
+// 16 sums as packed pairs in memory order.
+// ---------------------------------------------------------------------------
+template <int NP, bool PAIR>
+__device__ __forceinline__ void merge16(const uint4& c, const uint4 (&a)[NP], uint32_t (&out)[8]) {
+    const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+    uint32_t ev[4], od[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ev[q] = (cw[q] & 0x00FF00FFu) * (uint32_t)NP;
+        od[q] = ((cw[q] >> 8) & 0x00FF00FFu) * (uint32_t)NP;
+    }
+    constexpr int STEP = PAIR ? 2 : 1;
+#pragma unroll
+    for (int r = 0; r < NP; r += STEP) {
+        const uint32_t aw[4] = {a[r].x, a[r].y, a[r].z, a[r].w};
+        uint32_t sw[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sw[q] = aw[q];
+        if constexpr (PAIR) {
+            const uint32_t bw[4] = {a[r + 1].x, a[r + 1].y, a[r + 1].z, a[r + 1].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sw[q] += bw[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ev[q] += sw[q] & 0x00FF00FFu;
+            od[q] += (sw[q] >> 8) & 0x00FF00FFu;
+        }
+    }
+    // interleave back: elements e0 o0 e1 o1 of every source word
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        out[2 * q] = __builtin_amdgcn_perm(od[q], ev[q], 0x05040100u);
+        out[2 * q + 1] = __builtin_amdgcn_perm(od[q], ev[q], 0x07060302u);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // DPP controls (GFX9 encoding).  All stay inside a 16-lane row.
 // ---------------------------------------------------------------------------
 enum : int {
@@ -187,14 +231,21 @@ hipError_t launch_census(const Frame& f, bool right, hipStream_t stream);
 hipError_t launch_cost(const Frame& f, hipStream_t stream);
 hipError_t launch_aggregate(const Frame& f, hipStream_t stream);
 hipError_t launch_wta_lrc(const Frame& f, hipStream_t stream);
+// the path kernel of launch_aggregate alone (slices, no path sum)
+hipError_t launch_paths(const Frame& f, hipStream_t stream);
+// path sum fused with WTA / D^R / LR check / median, from the slices
+bool fused_select_supported(int ndisp, int npaths, int p2);
+hipError_t launch_aggregate_select(const Frame& f, hipStream_t stream);
 
 hipError_t launch_census_batch(const WorkList& wl, int win_w, int win_h, hipStream_t stream);
 hipError_t launch_cost_batch(const WorkList& wl, int ndisp, hipStream_t stream);
 hipError_t launch_paths_batch(const WorkList& wl, int ndisp, int npaths, int p2, int variant,
                               hipStream_t stream);
-hipError_t launch_merge_batch(const WorkList& wl, bool u8, hipStream_t stream);
+hipError_t launch_merge_batch(const WorkList& wl, int npaths, int p2, hipStream_t stream);
 hipError_t launch_fill_keys_batch(const WorkList& wl, hipStream_t stream);
 hipError_t launch_select_batch(const WorkList& wl, int ndisp, hipStream_t stream);
+hipError_t launch_select_fused_batch(const WorkList& wl, int ndisp, int npaths, int p2,
+                                     hipStream_t stream);
 hipError_t launch_median_batch(const WorkList& wl, hipStream_t stream);
 
 }  // namespace sgm

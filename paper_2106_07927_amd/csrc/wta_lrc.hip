@@ -83,32 +83,38 @@ struct SelectTile {
     uint32_t key[kSelectWaves][64][65];
 };
 
-// Segment of one wave: block (bx, y) of one frame; waves are independent.
-template <int EPL, bool VEC>
-__device__ __forceinline__ void select_block(SelectTile& st, const uint16_t* __restrict__ agg,
-                                             int width, int ndisp,
-                                             uint16_t* __restrict__ disp_left,
-                                             uint32_t* __restrict__ right_keys, int bx, int y) {
-    constexpr int K = 16;                      // pixels per load chunk
-    constexpr int kSeg = kSelectSeg;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int seg = bx * kSelectWaves + wave;
-    const int x0 = seg * kSeg;
-    if (x0 >= width) return;                       // uniform per wave
-    const int x1 = min(width, x0 + kSeg);
-    const size_t row = (size_t)y * width;
-    const int d0 = lane * EPL;
-    const int dlast_lane = (ndisp - 1) / EPL;
-    const int dlast_e = (ndisp - 1) % EPL;
-    uint32_t (*tl)[65] = st.key[wave];
-
+// Selection state of one wave over one row segment [x0, x1): the D^R chain,
+// the D^L tile and the keys waiting to be merged.
+template <int EPL>
+struct SelectWave {
+    uint32_t (*tl)[65];
+    uint16_t* disp_left;
+    uint32_t* right_keys;
+    size_t row;
+    int x0, x1, lane, d0, ndisp, dlast_lane, dlast_e;
     uint32_t T[EPL];
-#pragma unroll
-    for (int e = 0; e < EPL; ++e) T[e] = kInf;
-    uint32_t emit = kInf;                          // lane i: D^R key emitted at step base + i
+    uint32_t emit;                                 // lane i: D^R key emitted at step base + i
 
-    auto step = [&](const RawVals<EPL>& cv, int x) {
+    __device__ __forceinline__ void init(uint32_t (*tile)[65], uint16_t* dl, uint32_t* rk, int width,
+                                         int nd, int y, int seg_x0, int seg_x1) {
+        tl = tile;
+        disp_left = dl;
+        right_keys = rk;
+        row = (size_t)y * width;
+        x0 = seg_x0;
+        x1 = seg_x1;
+        lane = threadIdx.x & 63;
+        d0 = lane * EPL;
+        ndisp = nd;
+        dlast_lane = (nd - 1) / EPL;
+        dlast_e = (nd - 1) % EPL;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) T[e] = kInf;
+        emit = kInf;
+    }
+
+    // one pixel x of the segment, S_bar words of this lane's disparities
+    __device__ __forceinline__ void step(const RawVals<EPL>& cv, int x) {
         uint32_t key[EPL];
 #pragma unroll
         for (int e = 0; e < EPL; ++e)
@@ -144,13 +150,38 @@ __device__ __forceinline__ void select_block(SelectTile& st, const uint16_t* __r
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             emit = kInf;
         }
-    };
+    }
+
+    // partial minima still travelling through the lanes at the segment's end
+    __device__ __forceinline__ void finish() {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            const int d = d0 + e;
+            const int q = x1 - 1 - d;
+            if (d < ndisp - 1 && q >= 0 && T[e] != kInf) atomicMin(&right_keys[row + q], T[e]);
+        }
+    }
+};
+
+// Segment of one wave: block (bx, y) of one frame; waves are independent.
+template <int EPL, bool VEC>
+__device__ __forceinline__ void select_block(SelectTile& st, const uint16_t* __restrict__ agg,
+                                             int width, int ndisp,
+                                             uint16_t* __restrict__ disp_left,
+                                             uint32_t* __restrict__ right_keys, int bx, int y) {
+    constexpr int K = 16;                      // pixels per load chunk
+    const int wave = threadIdx.x >> 6;
+    const int x0 = (bx * kSelectWaves + wave) * kSelectSeg;
+    if (x0 >= width) return;                       // uniform per wave
+    const int x1 = min(width, x0 + kSelectSeg);
+    SelectWave<EPL> sw;
+    sw.init(st.key[wave], disp_left, right_keys, width, ndisp, y, x0, x1);
 
     int xl = x0;                                   // next pixel to load
     RawVals<EPL> nxt[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        nxt[j] = load_vals<EPL, VEC>(agg, row + xl, d0, ndisp);
+        nxt[j] = load_vals<EPL, VEC>(agg, sw.row + xl, sw.d0, ndisp);
         xl = min(xl + 1, x1 - 1);
     }
     for (int xc = x0; xc < x1; xc += K) {
@@ -159,21 +190,129 @@ __device__ __forceinline__ void select_block(SelectTile& st, const uint16_t* __r
         for (int j = 0; j < K; ++j) cur[j] = nxt[j];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            nxt[j] = load_vals<EPL, VEC>(agg, row + xl, d0, ndisp);
+            nxt[j] = load_vals<EPL, VEC>(agg, sw.row + xl, sw.d0, ndisp);
             xl = min(xl + 1, x1 - 1);
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int x = xc + j;
-            if (x < x1) step(cur[j], x);          // uniform
+            if (x < x1) sw.step(cur[j], x);       // uniform
         }
     }
-    // partial minima still travelling through the lanes
+    sw.finish();
+}
+
+// ---- path sum fused with the selection pass --------------------------------
+// The wave walks its segment in chunks of KP = 16 / EPL pixels, i.e. at most
+// 1024 volume elements: lane l sums the l-th 16-byte block of the chunk from
+// the cost volume and the NP uint8 penalty slices (merge16), parks the 16
+// sums in LDS, and then the chunk's pixels go through the same selection
+// steps as above, reading S_bar from LDS instead of HBM.  Loads run two
+// chunks ahead.  Needs D % 16 == 0, so every chunk starts on a 16-byte
+// boundary.
+constexpr int kFusedElems = 1024;
+
+struct FusedTile {
+    uint32_t key[kSelectWaves][64][65];
+    uint16_t sbar[kSelectWaves][kFusedElems];
+};
+
+template <int NP>
+struct ChunkRaw {
+    uint4 c;
+    uint4 a[NP];
+};
+
+template <int EPL, int NP, bool PAIR>
+__device__ __forceinline__ void select_fused_block(FusedTile& st, const Frame& f, int bx, int y) {
+    constexpr int KP = 16 / EPL;                   // pixels per chunk
+    const int wave = threadIdx.x >> 6;
+    const int width = f.width, ndisp = f.ndisp;
+    const int x0 = (bx * kSelectWaves + wave) * kSelectSeg;
+    if (x0 >= width) return;                       // uniform per wave
+    const int x1 = min(width, x0 + kSelectSeg);
+    SelectWave<EPL> sw;
+    sw.init(st.key[wave], f.disp_left, f.right_keys, width, ndisp, y, x0, x1);
+    uint16_t* sb = st.sbar[wave];
+    const int lane = sw.lane;
+
+    // element offsets: this lane's block of chunk c, clamped to the segment's
+    // last block (chunks past the end and idle lanes re-read it)
+    const uint32_t seg_e0 = (uint32_t)(sw.row + x0) * (uint32_t)ndisp;
+    const uint32_t last_blk = (uint32_t)(sw.row + x1) * (uint32_t)ndisp - 16u;
+    const uint8_t* slice[NP];
 #pragma unroll
-    for (int e = 0; e < EPL; ++e) {
-        const int d = d0 + e;
-        const int q = x1 - 1 - d;
-        if (d < ndisp - 1 && q >= 0 && T[e] != kInf) atomicMin(&right_keys[row + q], T[e]);
+    for (int r = 0; r < NP; ++r) slice[r] = f.slices + (size_t)r * f.slice_stride;
+    auto fetch = [&](int c) {
+        const uint32_t e = min(seg_e0 + (uint32_t)(c * KP * ndisp) + 16u * (uint32_t)lane, last_blk);
+        ChunkRaw<NP> raw;
+        raw.c = *reinterpret_cast<const uint4*>(f.cost + e);
+#pragma unroll
+        for (int r = 0; r < NP; ++r) raw.a[r] = *reinterpret_cast<const uint4*>(slice[r] + e);
+        return raw;
+    };
+    const int d0c = sw.d0 < ndisp ? sw.d0 : 0;
+    auto chunk = [&](const ChunkRaw<NP>& raw, int c) {
+        uint32_t s[8];
+        merge16<NP, PAIR>(raw.c, raw.a, s);
+        uint4* dst = reinterpret_cast<uint4*>(sb + 16 * lane);
+        dst[0] = make_uint4(s[0], s[1], s[2], s[3]);
+        dst[1] = make_uint4(s[4], s[5], s[6], s[7]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int xc = x0 + c * KP;
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+            const int x = xc + j;
+            if (x < x1) {                          // uniform
+                RawVals<EPL> cv;
+                const uint16_t* p = sb + j * ndisp + d0c;
+                if constexpr (EPL == 1) cv.w[0] = *p;
+                else if constexpr (EPL == 2) cv.w[0] = *reinterpret_cast<const uint32_t*>(p);
+                else {
+                    const uint2 w = *reinterpret_cast<const uint2*>(p);
+                    cv.w[0] = w.x;
+                    cv.w[1] = w.y;
+                }
+                sw.step(cv, x);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+
+    const int nch = (x1 - x0 + KP - 1) / KP;
+    ChunkRaw<NP> r0 = fetch(0), r1 = fetch(1);
+    for (int c = 0; c < nch; c += 2) {
+        const ChunkRaw<NP> a = r0;
+        r0 = fetch(c + 2);
+        chunk(a, c);
+        if (c + 1 < nch) {                         // uniform
+            const ChunkRaw<NP> b = r1;
+            r1 = fetch(c + 3);
+            chunk(b, c + 1);
+        }
+    }
+    sw.finish();
+}
+
+template <int EPL, int NP, bool PAIR>
+__global__ __launch_bounds__(64 * kSelectWaves) void select_fused_kernel(Frame f) {
+    __shared__ FusedTile st;
+    select_fused_block<EPL, NP, PAIR>(st, f, blockIdx.x, blockIdx.y);
+}
+
+template <int EPL, int NP, bool PAIR>
+__global__ __launch_bounds__(64 * kSelectWaves) void select_fused_batch_kernel(WorkList wl) {
+    __shared__ FusedTile st;
+    for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
+        const int fi = find_frame(wl, b);
+        const Frame& f = wl.frames[fi];
+        const int lb = b - wl.starts[fi];
+        const int bxs = select_blocks_x(f.width);
+        select_fused_block<EPL, NP, PAIR>(st, f, lb % bxs, lb / bxs);
     }
 }
 
@@ -321,7 +460,62 @@ void launch_select_any(const Frame* one, const WorkList* wl, int ndisp, hipStrea
     }
 }
 
+template <int EPL, int NP, bool PAIR>
+void launch_fused_t(const Frame* one, const WorkList* wl, hipStream_t stream) {
+    if (one) {
+        const dim3 g(select_blocks_x(one->width), one->height);
+        select_fused_kernel<EPL, NP, PAIR><<<g, 64 * kSelectWaves, 0, stream>>>(*one);
+    } else {
+        select_fused_batch_kernel<EPL, NP, PAIR>
+            <<<persistent_grid(wl->total, 2), 64 * kSelectWaves, 0, stream>>>(*wl);
+    }
+}
+
+template <int EPL>
+void launch_fused_epl(const Frame* one, const WorkList* wl, int npaths, int p2, hipStream_t stream) {
+    const bool pair = p2 <= 127;
+    if (npaths == 4) {
+        if (pair) launch_fused_t<EPL, 4, true>(one, wl, stream);
+        else launch_fused_t<EPL, 4, false>(one, wl, stream);
+    } else {
+        if (pair) launch_fused_t<EPL, 8, true>(one, wl, stream);
+        else launch_fused_t<EPL, 8, false>(one, wl, stream);
+    }
+}
+
+void launch_fused_any(const Frame* one, const WorkList* wl, int ndisp, int npaths, int p2,
+                      hipStream_t stream) {
+    if (ndisp <= 64) launch_fused_epl<1>(one, wl, npaths, p2, stream);
+    else if (ndisp <= 128) launch_fused_epl<2>(one, wl, npaths, p2, stream);
+    else launch_fused_epl<4>(one, wl, npaths, p2, stream);
+}
+
 }  // namespace
+
+bool fused_select_supported(int ndisp, int npaths, int p2) {
+    return ndisp % 16 == 0 && ndisp <= 256 && p2 <= 255 && (npaths == 4 || npaths == 8);
+}
+
+hipError_t launch_aggregate_select(const Frame& f, hipStream_t stream) {
+    hipError_t e = launch_paths(f, stream);
+    if (e != hipSuccess) return e;
+    const size_t n = (size_t)f.width * f.height;
+    fill_keys_kernel<<<fill_blocks(n), 256, 0, stream>>>(f);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    launch_fused_any(&f, nullptr, f.ndisp, f.npaths, f.p2, stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2(median_blocks_x(f.width), (f.height + kTH - 1) / kTH);
+    check_median_kernel<<<g2, 256, 0, stream>>>(f);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_fused_batch(const WorkList& wl, int ndisp, int npaths, int p2,
+                                     hipStream_t stream) {
+    launch_fused_any(nullptr, &wl, ndisp, npaths, p2, stream);
+    return hipGetLastError();
+}
 
 hipError_t launch_wta_lrc(const Frame& f, hipStream_t stream) {
     const size_t n = (size_t)f.width * f.height;

@@ -96,13 +96,21 @@ def make_trace(specs, rate_hz: float, duration_s: float, frames_per_stream: int,
     return reqs
 
 
+def _a256(b: int) -> int:
+    return (b + 255) // 256 * 256
+
+
 def slot_bytes(spec: StreamSpec, npaths: int, p2: int) -> int:
-    """Device bytes of one slot: inputs, census x2, cost, path slices, S_bar,
-    selection scratch, disparity maps (the buffers of one StereoSGM)."""
+    """Device bytes of one slot (the buffers of one StereoSGM): inputs,
+    census x2, cost, the workspace of the streamlined aggregation (path
+    slices, S_bar only where the fused selection does not apply, D^R keys,
+    D^L) and the two disparity maps."""
     n = spec.width * spec.height
     nd = spec.ndisp
-    slices = npaths * ((n * nd + 255) // 256 * 256) * (1 if p2 <= 255 else 2)
-    return 2 * n + 16 * n + n * nd + slices + 2 * n * nd + 6 * n + 4 * n
+    slices = npaths * _a256(n * nd) * (1 if p2 <= 255 else 2)
+    fused = nd % 16 == 0 and nd <= 256 and p2 <= 255
+    work = _a256(slices) + (0 if fused else _a256(2 * n * nd)) + _a256(4 * n) + _a256(2 * n)
+    return 2 * n + 16 * n + n * nd + work + 4 * n
 
 
 class Server:

@@ -6,7 +6,8 @@ is given.  All computation happens in the HIP kernels of libsgm.so; there is
 no fallback: if the library is not built, or a tensor is not on the GPU, the
 call raises.
 
-Names follow the C ABI: sgm_census, sgm_cost, sgm_aggregate, sgm_wta_lrc.
+Names follow the C ABI: sgm_census, sgm_cost, sgm_aggregate, sgm_wta_lrc, and
+the streamlined sgm_aggregate_select (aggregation fused with the selection).
 """
 from __future__ import annotations
 
@@ -29,7 +30,8 @@ SGM_ERR_HIP = -4
 SGM_ERR_WORKSPACE = -5
 
 EXPORTS = ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_aggregate_work_bytes", "sgm_wta_lrc",
-           "sgm_wta_lrc_work_elems", "sgm_batch_workspace_bytes", "sgm_batch_plan_create",
+           "sgm_wta_lrc_work_elems", "sgm_aggregate_select", "sgm_aggregate_select_work_bytes",
+           "sgm_batch_workspace_bytes", "sgm_batch_plan_create",
            "sgm_batch_run", "sgm_batch_frames", "sgm_batch_plan_destroy", "sgm_aggregate_variants",
            "sgm_status_string",
            "sgm_last_hip_error", "sgm_abi_version")
@@ -77,6 +79,10 @@ def load_library(path: str = LIB_PATH):
     lib.sgm_wta_lrc.argtypes = [P, I32, I32, I32, I32, I32, P, P, P, P]
     lib.sgm_wta_lrc_work_elems.argtypes = [I32, I32]
     lib.sgm_wta_lrc_work_elems.restype = ctypes.c_size_t
+    lib.sgm_aggregate_select.argtypes = [P, I32, I32, I32, I32, I32, I32, I32, I32, P, P, P,
+                                         ctypes.c_size_t, P]
+    lib.sgm_aggregate_select_work_bytes.argtypes = [I32, I32, I32, I32, I32]
+    lib.sgm_aggregate_select_work_bytes.restype = ctypes.c_size_t
     PP = ctypes.POINTER(SgmPair)
     lib.sgm_batch_workspace_bytes.argtypes = [PP, I32, ctypes.POINTER(SgmParams), ctypes.c_char_p]
     lib.sgm_batch_workspace_bytes.restype = ctypes.c_size_t
@@ -95,7 +101,7 @@ def load_library(path: str = LIB_PATH):
     lib.sgm_status_string.restype = ctypes.c_char_p
     lib.sgm_last_hip_error.argtypes = []
     lib.sgm_abi_version.argtypes = []
-    for name in ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_wta_lrc",
+    for name in ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_wta_lrc", "sgm_aggregate_select",
                  "sgm_last_hip_error", "sgm_abi_version"):
         getattr(lib, name).restype = I32
     if path == LIB_PATH:
@@ -222,6 +228,47 @@ def sgm_wta_lrc(agg: torch.Tensor, lr_tolerance: int, median3x3: bool,
     return out, out_right
 
 
+def aggregate_select_work_bytes(width: int, height: int, ndisp: int, npaths: int, p2: int) -> int:
+    return int(load_library().sgm_aggregate_select_work_bytes(width, height, ndisp, npaths, p2))
+
+
+def _aligned_bytes(nbytes: int, device, align: int = 256) -> torch.Tensor:
+    """uint8 device tensor of nbytes whose data pointer is align-byte aligned."""
+    raw = torch.empty(nbytes + align, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % align
+    return raw[off: off + nbytes]
+
+
+def sgm_aggregate_select(cost: torch.Tensor, npaths: int, p1: int, p2: int, lr_tolerance: int,
+                         median3x3: bool, out: Optional[torch.Tensor] = None,
+                         out_right: Optional[torch.Tensor] = None,
+                         work: Optional[torch.Tensor] = None, want_right: bool = False,
+                         stream=None):
+    """Aggregation fused with WTA, approximate D^R, LR check and median; the
+    path sum never reaches device memory.  Returns (disp, disp_right or None),
+    bit-identical to sgm_aggregate followed by sgm_wta_lrc.  `work`: uint8,
+    256-byte aligned, at least aggregate_select_work_bytes(...) bytes."""
+    if cost.dtype != torch.uint8 or cost.dim() != 3:
+        raise ValueError("cost must be a 3-D uint8 tensor")
+    h, w, nd = cost.shape
+    dev = cost.device
+    if out is None:
+        out = _empty((h, w), torch.uint16, dev)
+    _expect(out, torch.uint16, (h, w), "out")
+    if want_right and out_right is None:
+        out_right = _empty((h, w), torch.uint16, dev)
+    if out_right is not None:
+        _expect(out_right, torch.uint16, (h, w), "out_right")
+    if work is None:
+        work = _aligned_bytes(max(1, aggregate_select_work_bytes(w, h, nd, npaths, p2)), dev)
+    if work.dtype != torch.uint8:
+        raise ValueError("work must be a uint8 tensor")
+    _check(load_library().sgm_aggregate_select(_ptr(cost), w, h, nd, npaths, p1, p2, lr_tolerance,
+                                               int(bool(median3x3)), _ptr(out), _ptr(out_right),
+                                               _ptr(work), work.numel(), _stream(stream)))
+    return out, out_right
+
+
 @dataclass(frozen=True)
 class Params:
     """Pipeline parameters (lr_tolerance < 0 skips the LR check)."""
@@ -236,31 +283,44 @@ class Params:
 
 
 class StereoSGM:
-    """Device buffers for one frame shape, reused across frames; run() enqueues
-    the four ABI calls on one stream."""
+    """Device buffers for one frame shape, reused across frames.  run()
+    enqueues census (x2), cost and the streamlined sgm_aggregate_select on one
+    stream; with fused=False it enqueues the four calls sgm_census (x2),
+    sgm_cost, sgm_aggregate, sgm_wta_lrc instead (same bits, S_bar kept in
+    self.agg)."""
 
-    def __init__(self, width: int, height: int, params: Params, device="cuda"):
-        self.width, self.height, self.params = width, height, params
+    def __init__(self, width: int, height: int, params: Params, device="cuda", fused: bool = True):
+        self.width, self.height, self.params, self.fused = width, height, params, fused
         dev = torch.device(device)
         nd = params.ndisp
         self.census_left = _empty((height, width), torch.uint64, dev)
         self.census_right = _empty((height, width), torch.uint64, dev)
         self.cost = _empty((height, width, nd), torch.uint8, dev)
-        self.agg = _empty((height, width, nd), torch.uint16, dev)
-        self.agg_work = _empty((max(1, aggregate_work_bytes(width, height, nd, params.npaths, params.p2)),),
-                               torch.uint8, dev)
         self.disp = _empty((height, width), torch.uint16, dev)
         self.disp_right = _empty((height, width), torch.uint16, dev)
-        self.work = _empty((wta_lrc_work_elems(width, height),), torch.uint16, dev)
+        if fused:
+            self.select_work = _aligned_bytes(
+                max(1, aggregate_select_work_bytes(width, height, nd, params.npaths, params.p2)), dev)
+        else:
+            self.agg = _empty((height, width, nd), torch.uint16, dev)
+            self.agg_work = _empty((max(1, aggregate_work_bytes(width, height, nd, params.npaths,
+                                                                params.p2)),), torch.uint8, dev)
+            self.work = _empty((wta_lrc_work_elems(width, height),), torch.uint16, dev)
 
     def run(self, left: torch.Tensor, right: torch.Tensor, stream=None) -> torch.Tensor:
         p = self.params
         sgm_census(left, p.win_w, p.win_h, out=self.census_left, width=self.width, stream=stream)
         sgm_census(right, p.win_w, p.win_h, out=self.census_right, width=self.width, stream=stream)
         sgm_cost(self.census_left, self.census_right, p.ndisp, out=self.cost, stream=stream)
-        sgm_aggregate(self.cost, p.npaths, p.p1, p.p2, out=self.agg, work=self.agg_work, stream=stream)
-        sgm_wta_lrc(self.agg, p.lr_tolerance, p.median3x3, out=self.disp,
-                    out_right=self.disp_right, work=self.work, stream=stream)
+        if self.fused:
+            sgm_aggregate_select(self.cost, p.npaths, p.p1, p.p2, p.lr_tolerance, p.median3x3,
+                                 out=self.disp, out_right=self.disp_right, work=self.select_work,
+                                 stream=stream)
+        else:
+            sgm_aggregate(self.cost, p.npaths, p.p1, p.p2, out=self.agg, work=self.agg_work,
+                          stream=stream)
+            sgm_wta_lrc(self.agg, p.lr_tolerance, p.median3x3, out=self.disp,
+                        out_right=self.disp_right, work=self.work, stream=stream)
         return self.disp
 
 

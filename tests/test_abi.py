@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings_and_version(lib):
-    assert lib.sgm_abi_version() == 2
+    assert lib.sgm_abi_version() == 3
     for code in (OK, ARG, UNSUP, ALIGN, HIP, WS):
         assert lib.sgm_status_string(code).decode().startswith("SGM_")
     assert lib.sgm_status_string(99) == b"unknown sgm status"
@@ -110,6 +110,39 @@ def test_wta_lrc_validation(lib):
     assert lib.sgm_wta_lrc_work_elems(0, 20) == 0
 
 
+def test_aggregate_select_validation(lib):
+    f = lib.sgm_aggregate_select
+    W = lambda v: ctypes.c_size_t(v)
+    big = 1 << 40
+    args = lambda **k: [P(k.get("cost", FAKE)), k.get("w", 8), k.get("h", 8), k.get("nd", 16),
+                        k.get("npaths", 8), k.get("p1", 10), k.get("p2", 120), k.get("t", 1),
+                        k.get("med", 1), P(k.get("out", FAKE)), P(k.get("outr", NULL)),
+                        P(k.get("work", FAKE)), W(k.get("wb", big)), P(NULL)]
+    assert f(*args(cost=NULL)) == ARG
+    assert f(*args(out=NULL)) == ARG
+    assert f(*args(npaths=6)) == ARG
+    assert f(*args(p1=121)) == ARG
+    assert f(*args(p2=7937)) == ARG
+    assert f(*args(nd=0)) == ARG
+    assert f(*args(med=2)) == ARG
+    assert f(*args(work=NULL)) == WS
+    # fused form (D % 16 == 0, P2 <= 255): slices, D^R keys, D^L; no S_bar
+    n = 8 * 8
+    need = lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 120)
+    assert need == 8 * 1024 + 256 + 256
+    assert f(*args(wb=need - 1)) == WS
+    assert f(*args(work=FAKE + 16, wb=need)) == ALIGN           # 256-byte alignment
+    assert f(*args(cost=FAKE + 8, wb=need)) == ALIGN
+    assert f(*args(out=FAKE + 2, wb=need)) == ALIGN
+    assert f(*args(outr=FAKE + 2, wb=need)) == ALIGN
+    # unfused fallbacks also hold S_bar in the workspace
+    assert lib.sgm_aggregate_select_work_bytes(8, 8, 15, 8, 120) == \
+        8 * 1024 + (2 * n * 15 + 255) // 256 * 256 + 256 + 256
+    assert lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 256) == \
+        8 * 2048 + 2048 + 256 + 256
+    assert lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 7937) == 0
+
+
 def test_python_binding_rejects_host_tensors(lib):
     import torch
     img = torch.zeros(4, 4, dtype=torch.uint8)
@@ -123,9 +156,10 @@ def test_batch_validation(lib):
     pairs[0] = sgm.SgmPair(FAKE, FAKE, 64, 48, 64, 64, FAKE, None)
     pairs[1] = sgm.SgmPair(FAKE, FAKE, 32, 16, 40, 16, FAKE, FAKE)
     need = lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(prm), None)
-    # two frames of intermediates (census x2, cost, slices, agg, keys, D^L) plus tables
+    # two frames of intermediates (census x2, cost, slices, keys, D^L; S_bar
+    # only for frames that cannot take the fused selection) plus tables
     n0, n1 = 64 * 48, 32 * 16
-    lower = sum(8 * 2 * n + n * nd + 8 * n * nd + 2 * n * nd + 4 * n + 2 * n
+    lower = sum(8 * 2 * n + n * nd + 8 * n * nd + 4 * n + 2 * n
                 for n, nd in ((n0, 64), (n1, 16)))
     assert need >= lower
     # a tuning table that splits the path launches needs more table space

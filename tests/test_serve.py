@@ -73,3 +73,19 @@ def test_continuous_batching_beats_fifo_on_latency():
     mix = Server(sp, FakeBackend(sp, mdes_per_s=3e4), budget_bytes=1 << 40).run(trace)
     fifo = serve.serve_plain(trace, sp, FakeBackend(sp, mdes_per_s=3e4))
     assert np.percentile(mix.latencies_ms(), 99) <= np.percentile(fifo.latencies_ms(), 99)
+
+
+def test_slot_bytes_match_the_library_workspace():
+    """The scheduler's slot size uses the library's workspace formula."""
+    import os
+    from paper_2106_07927_amd import sgm
+    if not os.path.exists(sgm.LIB_PATH):
+        import pytest
+        pytest.skip("libsgm.so not built")
+    lib = sgm.load_library()
+    for sp in specs() + [StreamSpec(320, 240, 100, 5), StreamSpec(64, 48, 7, 6)]:
+        for p2 in (120, 300):
+            n = sp.width * sp.height
+            fixed = 2 * n + 16 * n + n * sp.ndisp + 4 * n
+            work = lib.sgm_aggregate_select_work_bytes(sp.width, sp.height, sp.ndisp, 8, p2)
+            assert serve.slot_bytes(sp, 8, p2) == fixed + work
