@@ -165,6 +165,33 @@ int32_t sgm_aggregate_select(const uint8_t* cost, int32_t width, int32_t height,
 size_t sgm_aggregate_select_work_bytes(int32_t width, int32_t height, int32_t ndisp,
                                        int32_t npaths, int32_t p2);
 
+/*
+ * sgm_aggregate_select with subpixel refinement (Sec. 2.1.3): every pixel's
+ * WTA disparity d gets the vertex offset of the parabola through S_bar at
+ * d - 1, d, d + 1,
+ *   off = (S(d-1) - S(d+1)) / (2 (S(d-1) - 2 S(d) + S(d+1))),  |off| <= 1/2,
+ * with off = 0 at d = 0, d = ndisp - 1 and where the three costs are equal;
+ * computed in float32 (IEEE division).  The LR check runs on the integer
+ * maps exactly as in sgm_wta_lrc; pixels it keeps take d + off; the 3x3
+ * median then runs over those float values, with pixels outside the image
+ * and invalid pixels counting as +inf (a median of +inf is invalid).
+ *   disp_out        float [height][width]; invalid pixels are -1.0f
+ *   disp_right_out  uint16 [height][width] (D^R) or NULL
+ *   work            sgm_aggregate_select_subpixel_work_bytes(...) bytes,
+ *                   256-byte aligned
+ * Other arguments and errors as for sgm_aggregate_select.
+ */
+int32_t sgm_aggregate_select_subpixel(const uint8_t* cost, int32_t width, int32_t height,
+                                      int32_t ndisp, int32_t npaths, int32_t p1, int32_t p2,
+                                      int32_t lr_tolerance, int32_t median3x3,
+                                      float* disp_out, uint16_t* disp_right_out,
+                                      void* work, size_t work_bytes, void* stream);
+
+/* Bytes of `work` that sgm_aggregate_select_subpixel needs (0 on invalid
+ * arguments). */
+size_t sgm_aggregate_select_subpixel_work_bytes(int32_t width, int32_t height, int32_t ndisp,
+                                                int32_t npaths, int32_t p2);
+
 /* ---------------------------------------------------------------------------
  * Batched form: many rectified pairs, each with its own size and disparity
  * range, run as one hipGraph launch.  Each pair's outputs are bit-identical
@@ -230,6 +257,38 @@ int32_t sgm_batch_frames(const sgm_plan* plan);
 /* Releases the graph and the plan's stream; the workspace stays the
  * caller's.  Accepts NULL. */
 void sgm_batch_plan_destroy(sgm_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * Exact consistency check (Sec. 2.1.3, occlusion detection; Sec. 3.1.3):
+ * D^R is not approximated from S_bar (Eq. right_disparity) but computed from
+ * scratch: the pair is swapped and flipped horizontally and matched again by
+ * the same census, cost, aggregation and WTA; that map, flipped back, is D^R
+ * in Eq. (LR_check).  The whole path from the two images:
+ *   D^L  = WTA of (left, right)
+ *   D^R(x, y) = WTA of (flip(right), flip(left)) at (width - 1 - x, y),
+ *               flip(I)(x, y) = I(width - 1 - x, y)
+ *   then Eq. (LR_check) with params->lr_tolerance (< 0: no check) and the
+ *   3x3 median as in sgm_wta_lrc.
+ *   left, right     uint8 [height][pitch_bytes] device images
+ *   params          census window, path set, penalties, tolerance, median
+ *                   (as sgm_params of the batched form)
+ *   disp_out        uint16 [height][width], 4-byte aligned
+ *   disp_right_out  uint16 [height][width] receiving the exact D^R, or NULL
+ *   work            device scratch of sgm_disparity_exact_lr_work_bytes(...)
+ *                   bytes, 256-byte aligned; contents on return unspecified
+ * Errors: SGM_ERR_ARG, SGM_ERR_UNSUPPORTED (window), SGM_ERR_WORKSPACE,
+ *         SGM_ERR_ALIGN, SGM_ERR_HIP.
+ * ------------------------------------------------------------------------- */
+int32_t sgm_disparity_exact_lr(const uint8_t* left, const uint8_t* right,
+                               int32_t width, int32_t height, int32_t pitch_bytes,
+                               int32_t ndisp, const sgm_params* params,
+                               uint16_t* disp_out, uint16_t* disp_right_out,
+                               void* work, size_t work_bytes, void* stream);
+
+/* Bytes of `work` that sgm_disparity_exact_lr needs (0 on invalid
+ * arguments). */
+size_t sgm_disparity_exact_lr_work_bytes(int32_t width, int32_t height, int32_t ndisp,
+                                         const sgm_params* params);
 
 /* Human-readable name of a status code. */
 const char* sgm_status_string(int32_t status);

@@ -221,3 +221,93 @@ def run(left: np.ndarray, right: np.ndarray, params: Params) -> dict:
         d = median3x3(d)
     return {"census_left": cl, "census_right": cr, "cost": c, "agg": agg,
             "disp_left": dl, "disp_right": dr, "disp": d}
+
+
+# ---------------------------------------------------------------------------
+# Exact right disparity map (Sec. 2.1.3, occlusion detection; Sec. 3.1.3):
+# instead of Eq. (right_disparity), the pair is swapped and flipped
+# horizontally and matched again by the same census, cost, aggregation and
+# WTA; the resulting map, flipped back, is D^R.
+# ---------------------------------------------------------------------------
+def exact_right_disparity(left: np.ndarray, right: np.ndarray, params: Params) -> np.ndarray:
+    """D^R from scratch: WTA of the swapped, horizontally flipped pair."""
+    ref = np.ascontiguousarray(right[:, ::-1])      # the right image becomes the reference
+    mat = np.ascontiguousarray(left[:, ::-1])
+    c = cost(census(ref, params.win_w, params.win_h), census(mat, params.win_w, params.win_h),
+             params.ndisp)
+    flipped = wta(aggregate(c, params.npaths, params.p1, params.p2))
+    return np.ascontiguousarray(flipped[:, ::-1])
+
+
+def run_exact_lr(left: np.ndarray, right: np.ndarray, params: Params) -> dict:
+    """The path with the exact consistency check: D^L of the pair, D^R of the
+    swapped and flipped pair, Eq. (LR_check), median."""
+    cl = census(left, params.win_w, params.win_h)
+    cr = census(right, params.win_w, params.win_h)
+    dl = wta(aggregate(cost(cl, cr, params.ndisp), params.npaths, params.p1, params.p2))
+    dr = exact_right_disparity(left, right, params)
+    d = lr_check(dl, dr, params.lr_tolerance) if params.lr_tolerance >= 0 else dl.copy()
+    if params.median3x3:
+        d = median3x3(d)
+    return {"disp_left": dl, "disp_right": dr, "disp": d}
+
+
+# ---------------------------------------------------------------------------
+# Subpixel refinement (Sec. 2.1.3): a parabola through the aggregated costs at
+# the WTA disparity d and at d - 1, d + 1; its vertex offset is added to d.
+# Floating point, here in float64.  Invalid pixels are -1.0.
+# ---------------------------------------------------------------------------
+INVALID_F = -1.0
+
+
+def subpixel_offset(s_prev: float, s_min: float, s_next: float) -> float:
+    """Vertex of the parabola through (-1, s_prev), (0, s_min), (1, s_next)."""
+    den = s_prev - 2.0 * s_min + s_next
+    if den <= 0.0:
+        return 0.0
+    return (s_prev - s_next) / (2.0 * den)
+
+
+def refine_subpixel(agg: np.ndarray, disp_left: np.ndarray) -> np.ndarray:
+    """d + offset for every pixel, from S_bar at d - 1, d, d + 1; no offset at
+    d = 0 or d = D - 1 (one neighbour is missing)."""
+    a = np.asarray(agg, np.float64)
+    h, w, nd = a.shape
+    d = np.asarray(disp_left, np.int64)
+    out = d.astype(np.float64)
+    inner = (d > 0) & (d < nd - 1)
+    ys, xs = np.nonzero(inner)
+    dd = d[ys, xs]
+    sp, s0, sn = a[ys, xs, dd - 1], a[ys, xs, dd], a[ys, xs, dd + 1]
+    den = sp - 2.0 * s0 + sn
+    off = np.where(den > 0, (sp - sn) / (2.0 * np.where(den > 0, den, 1.0)), 0.0)
+    out[ys, xs] += off
+    return out
+
+
+def median3x3_float(values: np.ndarray, valid: np.ndarray) -> np.ndarray:
+    """3x3 median of a float map (Sec. 2.1.3): invalid pixels stay invalid;
+    in the window, pixels outside the image and invalid pixels count as +inf;
+    a median of +inf is invalid."""
+    h, w = values.shape
+    v = np.where(valid, values, np.inf)
+    pad = np.full((h + 2, w + 2), np.inf)
+    pad[1:-1, 1:-1] = v
+    win = np.stack([pad[1 + dy: 1 + dy + h, 1 + dx: 1 + dx + w]
+                    for dy in (-1, 0, 1) for dx in (-1, 0, 1)], axis=-1)
+    med = np.sort(win, axis=-1)[..., 4]
+    out = np.where(valid & np.isfinite(med), med, INVALID_F)
+    return out
+
+
+def run_subpixel(left: np.ndarray, right: np.ndarray, params: Params) -> dict:
+    """The path with subpixel refinement: integer D^L, D^R and LR check as in
+    run(); surviving pixels take d + offset; then the float median."""
+    r = run(left, right, Params(**{**params.__dict__, "median3x3": False}))
+    fine = refine_subpixel(r["agg"], r["disp_left"])
+    valid = r["disp"] != INVALID
+    if params.median3x3:
+        d = median3x3_float(fine, valid)
+    else:
+        d = np.where(valid, fine, INVALID_F)
+    return {**r, "disp_fine": d}

@@ -1,6 +1,6 @@
 """Build libsgm.so (the gfx950 HIP kernels and the C ABI of include/sgm.h).
 
-    python -m paper_2106_07927_amd.build
+    python -m paper_2106_07927_amd.build [--incremental]
 
 Every source is compiled by hipcc for gfx950 only, in-tree, into
 ``paper_2106_07927_amd/libsgm.so``.  Packed-FP32 instruction selection is
@@ -9,6 +9,7 @@ switched off for the device code.
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -38,20 +39,52 @@ def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [_hipcc(), *COMMON]
     if src.endswith(".hip"):
-        cmd += ["-x", "hip", *DEVICE]
+        cmd += ["-x", "hip", *DEVICE, "-Rpass-analysis=kernel-resource-usage"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")
+    if src.endswith(".hip"):
+        _check_resources(src, res.stderr)
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libsgm.so; returns its path."""
+def _check_resources(src: str, remarks: str) -> None:
+    """Every kernel keeps its state in registers: a kernel with per-lane
+    scratch (spills or private arrays) fails the build."""
+    name = None
+    bad = []
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and int(m.group(1)) > 0:
+            bad.append(f"{name}: {m.group(1)} bytes/lane")
+    if bad:
+        raise RuntimeError(f"{src}: kernels with scratch memory:\n  " + "\n  ".join(bad))
+
+
+def _stale(src: str) -> bool:
+    """True when src's object is missing or older than src or any header."""
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)]
+    deps += [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE) if h.endswith(".h")]
+    return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (with incremental=True: only those whose object is
+    out of date) and link libsgm.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     sources = HIP_SOURCES + CPP_SOURCES
-    with ThreadPoolExecutor(max_workers=min(len(sources), 8)) as pool:
-        objs = list(pool.map(_compile, sources))
+    todo = [s for s in sources if not incremental or _stale(s)]
+    with ThreadPoolExecutor(max_workers=min(max(len(todo), 1), 8)) as pool:
+        list(pool.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in sources]
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -64,5 +97,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

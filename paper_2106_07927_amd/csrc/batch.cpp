@@ -80,8 +80,8 @@ int stage_blocks(Stage st, const Frame& f) {
         case kPaths: return path_blocks(f.width, f.height, f.ndisp, f.npaths, f.variant);
         case kMerge: return merge_blocks(n * f.ndisp);
         case kFill: return fill_blocks(n);
-        case kSelect:
-        case kFused: return select_blocks_x(f.width) * f.height;
+        case kSelect: return select_blocks_x(f.width) * f.height;
+        case kFused: return fused_blocks_x(f.width) * f.height;
         case kMedian: return median_blocks(f.width, f.height);
         default: return 0;
     }

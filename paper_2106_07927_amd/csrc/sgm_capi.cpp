@@ -58,6 +58,52 @@ size_t select_layout(int32_t width, int32_t height, int32_t ndisp, int32_t npath
     return off;
 }
 
+// The aggregation and selection of one frame: fused where it applies, else
+// sgm_aggregate + sgm_wta_lrc with S_bar in f.agg.
+hipError_t run_select(const sgm::Frame& f, hipStream_t s, bool fine = false) {
+    if (sgm::fused_select_supported(f.ndisp, f.npaths, f.p2))
+        return sgm::launch_aggregate_select(f, s, fine);
+    const hipError_t e = sgm::launch_aggregate(f, s);
+    if (e != hipSuccess) return e;
+    return fine ? sgm::launch_wta_lrc_fine(f, s) : sgm::launch_wta_lrc(f, s);
+}
+
+bool good_params(const sgm_params* p) {
+    if (!p) return false;
+    if (!((p->win_w == 5 && p->win_h == 5) || (p->win_w == 9 && p->win_h == 7))) return false;
+    if (bad_penalties(p->npaths, p->p1, p->p2)) return false;
+    return p->median3x3 == 0 || p->median3x3 == 1;
+}
+
+// Workspace of the exact-check path, byte offsets.
+struct ExactLayout {
+    size_t ref, mat, census_left, census_right, cost, select, agg, keys, dl, disp_left,
+        disp_flipped;
+};
+
+size_t exact_layout(int32_t width, int32_t height, int32_t ndisp, const sgm_params* p,
+                    ExactLayout* l) {
+    const size_t n = (size_t)width * height;
+    size_t off = 0;
+    l->ref = off;
+    off += align256(n);
+    l->mat = off;
+    off += align256(n);
+    l->census_left = off;
+    off += align256(8 * n);
+    l->census_right = off;
+    off += align256(8 * n);
+    l->cost = off;
+    off += align256(n * (size_t)ndisp);
+    l->select = off;
+    off += select_layout(width, height, ndisp, p->npaths, p->p2, &l->agg, &l->keys, &l->dl);
+    l->disp_left = off;
+    off += align256(2 * n);
+    l->disp_flipped = off;
+    off += align256(2 * n);
+    return off;
+}
+
 }  // namespace
 
 extern "C" {
@@ -209,12 +255,127 @@ int32_t sgm_aggregate_select(const uint8_t* cost, int32_t width, int32_t height,
     f.disp_left = reinterpret_cast<uint16_t*>(base + dl_off);
     f.disp = disp_out;
     f.disp_right = disp_right_out;
-    const hipStream_t s = as_stream(stream);
-    if (sgm::fused_select_supported(ndisp, npaths, p2)) return hip_status(sgm::launch_aggregate_select(f, s));
     f.agg = reinterpret_cast<uint16_t*>(base + agg_off);
-    const hipError_t e = sgm::launch_aggregate(f, s);
-    if (e != hipSuccess) return hip_status(e);
-    return hip_status(sgm::launch_wta_lrc(f, s));
+    return hip_status(run_select(f, as_stream(stream)));
+}
+
+size_t sgm_aggregate_select_subpixel_work_bytes(int32_t width, int32_t height, int32_t ndisp,
+                                                int32_t npaths, int32_t p2) {
+    const size_t base = sgm_aggregate_select_work_bytes(width, height, ndisp, npaths, p2);
+    return base ? base + align256(4 * (size_t)width * height) : 0;
+}
+
+int32_t sgm_aggregate_select_subpixel(const uint8_t* cost, int32_t width, int32_t height,
+                                      int32_t ndisp, int32_t npaths, int32_t p1, int32_t p2,
+                                      int32_t lr_tolerance, int32_t median3x3, float* disp_out,
+                                      uint16_t* disp_right_out, void* work, size_t work_bytes,
+                                      void* stream) {
+    if (!cost || !disp_out || bad_size(width, height)) return SGM_ERR_ARG;
+    if (bad_volume(width, height, ndisp) || bad_penalties(npaths, p1, p2)) return SGM_ERR_ARG;
+    if (median3x3 != 0 && median3x3 != 1) return SGM_ERR_ARG;
+    size_t agg_off, keys_off, dl_off;
+    const size_t fine_off = select_layout(width, height, ndisp, npaths, p2, &agg_off, &keys_off, &dl_off);
+    const size_t need = fine_off + align256(4 * (size_t)width * height);
+    if (!work || work_bytes < need) return SGM_ERR_WORKSPACE;
+    if (!aligned(cost, 16) || !aligned(work, 256) || !aligned(disp_out, 4) ||
+        (disp_right_out && !aligned(disp_right_out, 4)))
+        return SGM_ERR_ALIGN;
+    char* base = static_cast<char*>(work);
+    sgm::Frame f{};
+    f.width = width;
+    f.height = height;
+    f.ndisp = ndisp;
+    f.npaths = npaths;
+    f.p1 = p1;
+    f.p2 = p2;
+    f.lr_tolerance = lr_tolerance;
+    f.median3x3 = median3x3;
+    f.variant = 0;
+    f.cost = const_cast<uint8_t*>(cost);
+    f.slices = reinterpret_cast<uint8_t*>(base);
+    f.slice_stride = sgm::aggregate_slice_elems(width, height, ndisp);
+    f.agg = reinterpret_cast<uint16_t*>(base + agg_off);
+    f.right_keys = reinterpret_cast<uint32_t*>(base + keys_off);
+    f.disp_left = reinterpret_cast<uint16_t*>(base + dl_off);
+    f.fine_left = reinterpret_cast<float*>(base + fine_off);
+    f.disp_fine = disp_out;
+    f.disp_right = disp_right_out;
+    return hip_status(run_select(f, as_stream(stream), true));
+}
+
+size_t sgm_disparity_exact_lr_work_bytes(int32_t width, int32_t height, int32_t ndisp,
+                                         const sgm_params* params) {
+    if (bad_size(width, height) || bad_volume(width, height, ndisp) || !good_params(params)) return 0;
+    ExactLayout l;
+    return exact_layout(width, height, ndisp, params, &l);
+}
+
+int32_t sgm_disparity_exact_lr(const uint8_t* left, const uint8_t* right, int32_t width,
+                               int32_t height, int32_t pitch_bytes, int32_t ndisp,
+                               const sgm_params* params, uint16_t* disp_out,
+                               uint16_t* disp_right_out, void* work, size_t work_bytes,
+                               void* stream) {
+    if (!left || !right || !disp_out || bad_size(width, height) || pitch_bytes < width)
+        return SGM_ERR_ARG;
+    if (bad_volume(width, height, ndisp) || !params) return SGM_ERR_ARG;
+    if (!((params->win_w == 5 && params->win_h == 5) || (params->win_w == 9 && params->win_h == 7)))
+        return SGM_ERR_UNSUPPORTED;
+    if (!good_params(params)) return SGM_ERR_ARG;
+    ExactLayout l;
+    const size_t need = exact_layout(width, height, ndisp, params, &l);
+    if (!work || work_bytes < need) return SGM_ERR_WORKSPACE;
+    if (!aligned(work, 256) || !aligned(disp_out, 4) || (disp_right_out && !aligned(disp_right_out, 4)))
+        return SGM_ERR_ALIGN;
+    char* base = static_cast<char*>(work);
+    const hipStream_t s = as_stream(stream);
+    sgm::Frame f{};
+    f.width = width;
+    f.height = height;
+    f.ndisp = ndisp;
+    f.win_w = params->win_w;
+    f.win_h = params->win_h;
+    f.npaths = params->npaths;
+    f.p1 = params->p1;
+    f.p2 = params->p2;
+    f.variant = 0;
+    f.census_left = reinterpret_cast<uint64_t*>(base + l.census_left);
+    f.census_right = reinterpret_cast<uint64_t*>(base + l.census_right);
+    f.cost = reinterpret_cast<uint8_t*>(base + l.cost);
+    f.slices = reinterpret_cast<uint8_t*>(base + l.select);
+    f.slice_stride = sgm::aggregate_slice_elems(width, height, ndisp);
+    f.agg = reinterpret_cast<uint16_t*>(base + l.select + l.agg);
+    f.right_keys = reinterpret_cast<uint32_t*>(base + l.select + l.keys);
+    f.disp_left = reinterpret_cast<uint16_t*>(base + l.select + l.dl);
+    f.lr_tolerance = -1;            // both passes: plain WTA maps
+    f.median3x3 = 0;
+    f.disp_right = nullptr;
+    uint16_t* dl = reinterpret_cast<uint16_t*>(base + l.disp_left);
+    uint16_t* flipped = reinterpret_cast<uint16_t*>(base + l.disp_flipped);
+    uint8_t* ref = reinterpret_cast<uint8_t*>(base + l.ref);
+    uint8_t* mat = reinterpret_cast<uint8_t*>(base + l.mat);
+    hipError_t e = hipSuccess;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        if (pass == 0) {
+            f.left = left;
+            f.right = right;
+            f.pitch = pitch_bytes;
+            f.disp = dl;
+        } else {
+            e = sgm::launch_flip_pair(left, right, width, height, pitch_bytes, ref, mat, s);
+            f.left = ref;
+            f.right = mat;
+            f.pitch = width;
+            f.disp = flipped;
+        }
+        if (e == hipSuccess) e = sgm::launch_census(f, false, s);
+        if (e == hipSuccess) e = sgm::launch_census(f, true, s);
+        if (e == hipSuccess) e = sgm::launch_cost(f, s);
+        if (e == hipSuccess) e = run_select(f, s);
+    }
+    if (e == hipSuccess)
+        e = sgm::launch_check_exact(dl, flipped, width, height, params->lr_tolerance,
+                                    params->median3x3, disp_out, disp_right_out, s);
+    return hip_status(e);
 }
 
 }  // extern "C"

@@ -151,6 +151,8 @@ struct Frame {
     uint16_t* disp_left;             // D^L, width*height
     uint16_t* disp;
     uint16_t* disp_right;            // may be null
+    float* fine_left;                // subpixel forms: refined D^L, width*height
+    float* disp_fine;                // subpixel forms: output map
 };
 
 // A launch over several frames: block b of the launch belongs to the frame f
@@ -198,6 +200,16 @@ __host__ __device__ inline int select_blocks_x(int w) {
     return (segs + kSelectWaves - 1) / kSelectWaves;
 }
 
+// row segment of one wave in the fused path-sum + selection pass
+#ifndef SGM_FUSED_SEG
+#define SGM_FUSED_SEG 128
+#endif
+constexpr int kFusedSeg = SGM_FUSED_SEG;
+__host__ __device__ inline int fused_blocks_x(int w) {
+    const int segs = (w + kFusedSeg - 1) / kFusedSeg;
+    return (segs + kSelectWaves - 1) / kSelectWaves;
+}
+
 constexpr int kMedianTileW = 64;
 constexpr int kMedianTileH = 4;
 __host__ __device__ inline int median_blocks_x(int w) { return (w + kMedianTileW - 1) / kMedianTileW; }
@@ -235,7 +247,16 @@ hipError_t launch_wta_lrc(const Frame& f, hipStream_t stream);
 hipError_t launch_paths(const Frame& f, hipStream_t stream);
 // path sum fused with WTA / D^R / LR check / median, from the slices
 bool fused_select_supported(int ndisp, int npaths, int p2);
-hipError_t launch_aggregate_select(const Frame& f, hipStream_t stream);
+hipError_t launch_aggregate_select(const Frame& f, hipStream_t stream, bool fine = false);
+// selection with subpixel refinement from S_bar in f.agg (float output)
+hipError_t launch_wta_lrc_fine(const Frame& f, hipStream_t stream);
+// exact consistency check: the swapped, flipped pair and the check against
+// its WTA map
+hipError_t launch_flip_pair(const uint8_t* left, const uint8_t* right, int width, int height,
+                            int pitch, uint8_t* ref, uint8_t* mat, hipStream_t stream);
+hipError_t launch_check_exact(const uint16_t* disp_left, const uint16_t* flipped, int width,
+                              int height, int tolerance, int median, uint16_t* disp,
+                              uint16_t* disp_right, hipStream_t stream);
 
 hipError_t launch_census_batch(const WorkList& wl, int win_w, int win_h, hipStream_t stream);
 hipError_t launch_cost_batch(const WorkList& wl, int ndisp, hipStream_t stream);

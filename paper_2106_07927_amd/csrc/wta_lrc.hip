@@ -70,35 +70,71 @@ __device__ __forceinline__ uint32_t val(const RawVals<EPL>& r, int e) {
     return (e & 1) ? (r.w[e >> 1] >> 16) : (r.w[e >> 1] & 0xFFFFu);
 }
 
-// T[e] for a wave-uniform e, without indexing a register array
-template <int EPL>
-__device__ __forceinline__ uint32_t pick(const uint32_t (&T)[EPL], int e) {
-    uint32_t r = T[0];
-#pragma unroll
-    for (int i = 1; i < EPL; ++i) r = (e == i) ? T[i] : r;
-    return r;
-}
-
+// LDS of a selection block: the D^L tile of every wave (none with FINE).
+template <bool FINE>
 struct SelectTile {
     uint32_t key[kSelectWaves][64][65];
 };
+template <>
+struct SelectTile<true> {
+    uint32_t key[kSelectWaves][1][65];
+};
+
+// Minimum over the 64 lanes of the wave, returned to every lane.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = group_min<16>(v);
+    auto s16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = min((uint32_t)s16[0], (uint32_t)s16[1]);
+    auto s32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return min((uint32_t)s32[0], (uint32_t)s32[1]);
+}
+
+// S_bar of disparity d (wave-uniform) of the current pixel, from the lane
+// that holds it.
+template <int EPL>
+__device__ __forceinline__ uint32_t value_of(const RawVals<EPL>& cv, int d) {
+    const int ln = d / EPL;
+    const int e = d - ln * EPL;
+    uint32_t v = val<EPL>(cv, 0);
+#pragma unroll
+    for (int i = 1; i < EPL; ++i) v = (e == i) ? val<EPL>(cv, i) : v;
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, ln);
+}
+
+// Subpixel refinement (Sec. 2.1.3): d plus the vertex offset of the parabola
+// through S_bar at d - 1, d, d + 1; no offset at either end of the range or
+// when the three costs are equal.
+__device__ __forceinline__ float refine(int d, uint32_t s_prev, uint32_t s_min, uint32_t s_next) {
+    const float den = (float)s_prev - 2.0f * (float)s_min + (float)s_next;
+    const float off = den > 0.0f ? ((float)s_prev - (float)s_next) / (2.0f * den) : 0.0f;
+    return (float)d + off;
+}
 
 // Selection state of one wave over one row segment [x0, x1): the D^R chain,
-// the D^L tile and the keys waiting to be merged.
-template <int EPL>
+// the D^L tile and the keys waiting to be merged.  With FINE, D^L comes from
+// a wave-wide minimum at every pixel instead of the tile (the winner's
+// neighbours are needed at once for the subpixel refinement), and the
+// refined D^L is written beside it.
+template <int EPL, bool FINE>
 struct SelectWave {
     uint32_t (*tl)[65];
     uint16_t* disp_left;
+    float* fine_left;
     uint32_t* right_keys;
     size_t row;
     int x0, x1, lane, d0, ndisp, dlast_lane, dlast_e;
-    uint32_t T[EPL];
+    // D^R chain, one entry per disparity of the lane; a vector type so that
+    // the wave-uniform pick of entry dlast_e stays in registers
+    uint32_t T __attribute__((ext_vector_type(EPL)));
     uint32_t emit;                                 // lane i: D^R key emitted at step base + i
+    uint32_t dl_slot;                              // FINE: lane i holds D^L of pixel base + i
+    float fine_slot;                               //        and its refined value
 
-    __device__ __forceinline__ void init(uint32_t (*tile)[65], uint16_t* dl, uint32_t* rk, int width,
-                                         int nd, int y, int seg_x0, int seg_x1) {
+    __device__ __forceinline__ void init(uint32_t (*tile)[65], uint16_t* dl, float* fl, uint32_t* rk,
+                                         int width, int nd, int y, int seg_x0, int seg_x1) {
         tl = tile;
         disp_left = dl;
+        fine_left = fl;
         right_keys = rk;
         row = (size_t)y * width;
         x0 = seg_x0;
@@ -111,6 +147,8 @@ struct SelectWave {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) T[e] = kInf;
         emit = kInf;
+        dl_slot = 0;
+        fine_slot = 0.0f;
     }
 
     // one pixel x of the segment, S_bar words of this lane's disparities
@@ -123,31 +161,50 @@ struct SelectWave {
 #pragma unroll
         for (int e = 1; e < EPL; ++e) k = min(k, key[e]);
         const int slot = (x - x0) & 63;
-        tl[slot][lane] = k;
+        if constexpr (FINE) {
+            const uint32_t best = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min(k));
+            const int d = (int)(best & 0xFFu);
+            float f = (float)d;
+            if (d > 0 && d < ndisp - 1)          // uniform
+                f = refine(d, value_of<EPL>(cv, d - 1), best >> 8, value_of<EPL>(cv, d + 1));
+            dl_slot = (lane == slot) ? (uint32_t)d : dl_slot;
+            fine_slot = (lane == slot) ? f : fine_slot;
+        } else {
+            tl[slot][lane] = k;
+        }
         // D^R chain: T_d <- min(T_{d-1}, key_d)
         const uint32_t carry = wave_shr1(T[EPL - 1], kInf);
 #pragma unroll
         for (int e = EPL - 1; e >= 1; --e) T[e] = min(T[e - 1], key[e]);
         T[0] = min(lane == 0 ? kInf : carry, key[0]);
-        const uint32_t done = __builtin_amdgcn_readlane(pick<EPL>(T, dlast_e), dlast_lane);
+        const uint32_t done = __builtin_amdgcn_readlane(T[dlast_e], dlast_lane);
         emit = (lane == slot) ? done : emit;
         if (slot == 63 || x == x1 - 1) {
-            // D^L of the pixels base .. x: lane i reduces row i of the tile
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int base = x - slot;
-            if (lane <= slot) {
-                uint32_t best = tl[lane][0];
+            if constexpr (FINE) {
+                if (lane <= slot) {
+                    disp_left[row + base + lane] = (uint16_t)dl_slot;
+                    fine_left[row + base + lane] = fine_slot;
+                    const int q = base + lane - (ndisp - 1);
+                    if (q >= 0) atomicMin(&right_keys[row + q], emit);
+                }
+            } else {
+                // D^L of the pixels base .. x: lane i reduces row i of the tile
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane <= slot) {
+                    uint32_t best = tl[lane][0];
 #pragma unroll 8
-                for (int i = 1; i < 64; ++i) best = min(best, tl[lane][i]);
-                disp_left[row + base + lane] = (uint16_t)(best & 0xFFu);
-                const int q = base + lane - (ndisp - 1);
-                if (q >= 0) atomicMin(&right_keys[row + q], emit);
+                    for (int i = 1; i < 64; ++i) best = min(best, tl[lane][i]);
+                    disp_left[row + base + lane] = (uint16_t)(best & 0xFFu);
+                    const int q = base + lane - (ndisp - 1);
+                    if (q >= 0) atomicMin(&right_keys[row + q], emit);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             emit = kInf;
         }
     }
@@ -164,18 +221,19 @@ struct SelectWave {
 };
 
 // Segment of one wave: block (bx, y) of one frame; waves are independent.
-template <int EPL, bool VEC>
-__device__ __forceinline__ void select_block(SelectTile& st, const uint16_t* __restrict__ agg,
+template <int EPL, bool VEC, bool FINE>
+__device__ __forceinline__ void select_block(SelectTile<FINE>& st, const uint16_t* __restrict__ agg,
                                              int width, int ndisp,
                                              uint16_t* __restrict__ disp_left,
+                                             float* __restrict__ fine_left,
                                              uint32_t* __restrict__ right_keys, int bx, int y) {
     constexpr int K = 16;                      // pixels per load chunk
     const int wave = threadIdx.x >> 6;
     const int x0 = (bx * kSelectWaves + wave) * kSelectSeg;
     if (x0 >= width) return;                       // uniform per wave
     const int x1 = min(width, x0 + kSelectSeg);
-    SelectWave<EPL> sw;
-    sw.init(st.key[wave], disp_left, right_keys, width, ndisp, y, x0, x1);
+    SelectWave<EPL, FINE> sw;
+    sw.init(st.key[wave], disp_left, fine_left, right_keys, width, ndisp, y, x0, x1);
 
     int xl = x0;                                   // next pixel to load
     RawVals<EPL> nxt[K];
@@ -207,13 +265,18 @@ __device__ __forceinline__ void select_block(SelectTile& st, const uint16_t* __r
 // 1024 volume elements: lane l sums the l-th 16-byte block of the chunk from
 // the cost volume and the NP uint8 penalty slices (merge16), parks the 16
 // sums in LDS, and then the chunk's pixels go through the same selection
-// steps as above, reading S_bar from LDS instead of HBM.  Loads run two
-// chunks ahead.  Needs D % 16 == 0, so every chunk starts on a 16-byte
-// boundary.
+// steps as above, reading S_bar from LDS instead of HBM.  Loads run
+// kFusedPrefetch chunks ahead.  Needs D % 16 == 0, so every chunk starts on a
+// 16-byte boundary.
 constexpr int kFusedElems = 1024;
+#ifndef SGM_FUSED_PREFETCH
+#define SGM_FUSED_PREFETCH 2
+#endif
+constexpr int kFusedPrefetch = SGM_FUSED_PREFETCH;
 
+template <bool FINE>
 struct FusedTile {
-    uint32_t key[kSelectWaves][64][65];
+    SelectTile<FINE> sel;
     uint16_t sbar[kSelectWaves][kFusedElems];
 };
 
@@ -223,16 +286,16 @@ struct ChunkRaw {
     uint4 a[NP];
 };
 
-template <int EPL, int NP, bool PAIR>
-__device__ __forceinline__ void select_fused_block(FusedTile& st, const Frame& f, int bx, int y) {
+template <int EPL, int NP, bool PAIR, bool FINE>
+__device__ __forceinline__ void select_fused_block(FusedTile<FINE>& st, const Frame& f, int bx, int y) {
     constexpr int KP = 16 / EPL;                   // pixels per chunk
     const int wave = threadIdx.x >> 6;
     const int width = f.width, ndisp = f.ndisp;
-    const int x0 = (bx * kSelectWaves + wave) * kSelectSeg;
+    const int x0 = (bx * kSelectWaves + wave) * kFusedSeg;
     if (x0 >= width) return;                       // uniform per wave
-    const int x1 = min(width, x0 + kSelectSeg);
-    SelectWave<EPL> sw;
-    sw.init(st.key[wave], f.disp_left, f.right_keys, width, ndisp, y, x0, x1);
+    const int x1 = min(width, x0 + kFusedSeg);
+    SelectWave<EPL, FINE> sw;
+    sw.init(st.sel.key[wave], f.disp_left, f.fine_left, f.right_keys, width, ndisp, y, x0, x1);
     uint16_t* sb = st.sbar[wave];
     const int lane = sw.lane;
 
@@ -284,53 +347,58 @@ __device__ __forceinline__ void select_fused_block(FusedTile& st, const Frame& f
     };
 
     const int nch = (x1 - x0 + KP - 1) / KP;
-    ChunkRaw<NP> r0 = fetch(0), r1 = fetch(1);
-    for (int c = 0; c < nch; c += 2) {
-        const ChunkRaw<NP> a = r0;
-        r0 = fetch(c + 2);
-        chunk(a, c);
-        if (c + 1 < nch) {                         // uniform
-            const ChunkRaw<NP> b = r1;
-            r1 = fetch(c + 3);
-            chunk(b, c + 1);
+    ChunkRaw<NP> ring[kFusedPrefetch];
+#pragma unroll
+    for (int p = 0; p < kFusedPrefetch; ++p) ring[p] = fetch(p);
+    for (int c0 = 0; c0 < nch; c0 += kFusedPrefetch) {
+#pragma unroll
+        for (int p = 0; p < kFusedPrefetch; ++p) {
+            const int c = c0 + p;
+            if (c < nch) {                         // uniform
+                const ChunkRaw<NP> raw = ring[p];
+                ring[p] = fetch(c + kFusedPrefetch);
+                chunk(raw, c);
+            }
         }
     }
     sw.finish();
 }
 
-template <int EPL, int NP, bool PAIR>
+template <int EPL, int NP, bool PAIR, bool FINE>
 __global__ __launch_bounds__(64 * kSelectWaves) void select_fused_kernel(Frame f) {
-    __shared__ FusedTile st;
-    select_fused_block<EPL, NP, PAIR>(st, f, blockIdx.x, blockIdx.y);
+    __shared__ FusedTile<FINE> st;
+    select_fused_block<EPL, NP, PAIR, FINE>(st, f, blockIdx.x, blockIdx.y);
 }
 
 template <int EPL, int NP, bool PAIR>
 __global__ __launch_bounds__(64 * kSelectWaves) void select_fused_batch_kernel(WorkList wl) {
-    __shared__ FusedTile st;
+    __shared__ FusedTile<false> st;
     for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
         const int fi = find_frame(wl, b);
         const Frame& f = wl.frames[fi];
         const int lb = b - wl.starts[fi];
-        const int bxs = select_blocks_x(f.width);
-        select_fused_block<EPL, NP, PAIR>(st, f, lb % bxs, lb / bxs);
+        const int bxs = fused_blocks_x(f.width);
+        select_fused_block<EPL, NP, PAIR, false>(st, f, lb % bxs, lb / bxs);
     }
 }
 
-template <int EPL, bool VEC>
+template <int EPL, bool VEC, bool FINE>
 __global__ __launch_bounds__(64 * kSelectWaves) void select_kernel(Frame f) {
-    __shared__ SelectTile st;
-    select_block<EPL, VEC>(st, f.agg, f.width, f.ndisp, f.disp_left, f.right_keys, blockIdx.x, blockIdx.y);
+    __shared__ SelectTile<FINE> st;
+    select_block<EPL, VEC, FINE>(st, f.agg, f.width, f.ndisp, f.disp_left, f.fine_left, f.right_keys,
+                                 blockIdx.x, blockIdx.y);
 }
 
 template <int EPL, bool VEC>
 __global__ __launch_bounds__(64 * kSelectWaves) void select_batch_kernel(WorkList wl) {
-    __shared__ SelectTile st;
+    __shared__ SelectTile<false> st;
     for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
         const int fi = find_frame(wl, b);
         const Frame& f = wl.frames[fi];
         const int lb = b - wl.starts[fi];
         const int bxs = select_blocks_x(f.width);
-        select_block<EPL, VEC>(st, f.agg, f.width, f.ndisp, f.disp_left, f.right_keys, lb % bxs, lb / bxs);
+        select_block<EPL, VEC, false>(st, f.agg, f.width, f.ndisp, f.disp_left, nullptr, f.right_keys,
+                                      lb % bxs, lb / bxs);
     }
 }
 
@@ -371,9 +439,20 @@ struct MedianTile {
     uint16_t v[(kTH + 2) * (kTW + 2)];
 };
 
+// D^R of pixel (xr, row): from the key map of the approximate D^R, or, for the
+// exact check, from the disparity map of the swapped, flipped pair.
+struct RightSource {
+    const uint32_t* keys;            // approximate: key & 0xFF
+    const uint16_t* flipped;         // exact: flipped[row][width - 1 - xr]
+    __device__ __forceinline__ int at(size_t row, int xr, int width) const {
+        if (flipped) return flipped[row + (width - 1 - xr)];
+        return (int)(keys[row + xr] & 0xFFu);
+    }
+};
+
 __device__ __forceinline__ void check_median_block(MedianTile& mt, const uint16_t* __restrict__ disp_left,
-                                                   const uint32_t* __restrict__ right_keys,
-                                                   int width, int height, int tolerance, int median,
+                                                   RightSource rs, int width, int height,
+                                                   int tolerance, int median,
                                                    uint16_t* __restrict__ disp,
                                                    uint16_t* __restrict__ disp_right, int bx, int by) {
     uint16_t* tile = mt.v;
@@ -390,7 +469,7 @@ __device__ __forceinline__ void check_median_block(MedianTile& mt, const uint16_
                 const int xr = gx - dl;
                 v = kInvalid;
                 if (xr >= 0) {
-                    const int dr = (int)(right_keys[row + xr] & 0xFFu);
+                    const int dr = rs.at(row, xr, width);
                     const int diff = dl > dr ? dl - dr : dr - dl;
                     if (diff <= tolerance) v = (uint16_t)dl;
                 }
@@ -413,17 +492,17 @@ __device__ __forceinline__ void check_median_block(MedianTile& mt, const uint16_
                 for (int dx = -1; dx <= 1; ++dx) v[k++] = c[dy * (kTW + 2) + dx];
             out = (uint16_t)median9(v);
         }
-        const size_t idx = (size_t)gy * width + gx;
-        disp[idx] = out;
-        if (disp_right) disp_right[idx] = (uint16_t)(right_keys[idx] & 0xFFu);
+        const size_t row = (size_t)gy * width;
+        disp[row + gx] = out;
+        if (disp_right) disp_right[row + gx] = (uint16_t)rs.at(row, gx, width);
     }
     __syncthreads();   // the tile is reused by the next work item
 }
 
 __global__ __launch_bounds__(256) void check_median_kernel(Frame f) {
     __shared__ MedianTile mt;
-    check_median_block(mt, f.disp_left, f.right_keys, f.width, f.height, f.lr_tolerance,
-                       f.median3x3, f.disp, f.disp_right, blockIdx.x, blockIdx.y);
+    check_median_block(mt, f.disp_left, RightSource{f.right_keys, nullptr}, f.width, f.height,
+                       f.lr_tolerance, f.median3x3, f.disp, f.disp_right, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(256) void check_median_batch_kernel(WorkList wl) {
@@ -433,61 +512,161 @@ __global__ __launch_bounds__(256) void check_median_batch_kernel(WorkList wl) {
         const Frame& f = wl.frames[fi];
         const int lb = b - wl.starts[fi];
         const int bxs = median_blocks_x(f.width);
-        check_median_block(mt, f.disp_left, f.right_keys, f.width, f.height, f.lr_tolerance,
-                           f.median3x3, f.disp, f.disp_right, lb % bxs, lb / bxs);
+        check_median_block(mt, f.disp_left, RightSource{f.right_keys, nullptr}, f.width, f.height,
+                           f.lr_tolerance, f.median3x3, f.disp, f.disp_right, lb % bxs, lb / bxs);
     }
 }
 
-template <int EPL, bool VEC>
+// Exact consistency check: disp_left = D^L of the pair, flipped = the WTA map
+// of the swapped, horizontally flipped pair (so D^R(xr) = flipped[W-1-xr]).
+__global__ __launch_bounds__(256) void check_median_exact_kernel(const uint16_t* __restrict__ disp_left,
+                                                                  const uint16_t* __restrict__ flipped,
+                                                                  int width, int height, int tolerance,
+                                                                  int median, uint16_t* __restrict__ disp,
+                                                                  uint16_t* __restrict__ disp_right) {
+    __shared__ MedianTile mt;
+    check_median_block(mt, disp_left, RightSource{nullptr, flipped}, width, height, tolerance, median,
+                       disp, disp_right, blockIdx.x, blockIdx.y);
+}
+
+// The swapped, horizontally flipped pair: ref[y][x] = right[y][W-1-x] (the
+// new reference image), mat[y][x] = left[y][W-1-x].  Outputs have pitch W.
+__global__ __launch_bounds__(256) void flip_pair_kernel(const uint8_t* __restrict__ left,
+                                                        const uint8_t* __restrict__ right, int width,
+                                                        int height, int pitch,
+                                                        uint8_t* __restrict__ ref,
+                                                        uint8_t* __restrict__ mat) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= width) return;
+    const size_t src = (size_t)y * pitch + (width - 1 - x);
+    const size_t dst = (size_t)y * width + x;
+    ref[dst] = right[src];
+    mat[dst] = left[src];
+}
+
+template <int EPL, bool VEC, bool FINE>
 void launch_select_t(const Frame* one, const WorkList* wl, hipStream_t stream) {
     if (one) {
         const dim3 g(select_blocks_x(one->width), one->height);
-        select_kernel<EPL, VEC><<<g, 64 * kSelectWaves, 0, stream>>>(*one);
+        select_kernel<EPL, VEC, FINE><<<g, 64 * kSelectWaves, 0, stream>>>(*one);
     } else {
         select_batch_kernel<EPL, VEC><<<persistent_grid(wl->total, 2), 64 * kSelectWaves, 0, stream>>>(*wl);
     }
 }
 
+template <bool FINE>
 void launch_select_any(const Frame* one, const WorkList* wl, int ndisp, hipStream_t stream) {
     if (ndisp <= 64) {
-        launch_select_t<1, true>(one, wl, stream);
+        launch_select_t<1, true, FINE>(one, wl, stream);
     } else if (ndisp <= 128) {
-        if (ndisp % 2 == 0) launch_select_t<2, true>(one, wl, stream);
-        else launch_select_t<2, false>(one, wl, stream);
+        if (ndisp % 2 == 0) launch_select_t<2, true, FINE>(one, wl, stream);
+        else launch_select_t<2, false, FINE>(one, wl, stream);
     } else {
-        if (ndisp % 4 == 0) launch_select_t<4, true>(one, wl, stream);
-        else launch_select_t<4, false>(one, wl, stream);
+        if (ndisp % 4 == 0) launch_select_t<4, true, FINE>(one, wl, stream);
+        else launch_select_t<4, false, FINE>(one, wl, stream);
     }
 }
 
-template <int EPL, int NP, bool PAIR>
+template <int EPL, int NP, bool PAIR, bool FINE>
 void launch_fused_t(const Frame* one, const WorkList* wl, hipStream_t stream) {
     if (one) {
-        const dim3 g(select_blocks_x(one->width), one->height);
-        select_fused_kernel<EPL, NP, PAIR><<<g, 64 * kSelectWaves, 0, stream>>>(*one);
+        const dim3 g(fused_blocks_x(one->width), one->height);
+        select_fused_kernel<EPL, NP, PAIR, FINE><<<g, 64 * kSelectWaves, 0, stream>>>(*one);
     } else {
         select_fused_batch_kernel<EPL, NP, PAIR>
             <<<persistent_grid(wl->total, 2), 64 * kSelectWaves, 0, stream>>>(*wl);
     }
 }
 
-template <int EPL>
+template <int EPL, bool FINE>
 void launch_fused_epl(const Frame* one, const WorkList* wl, int npaths, int p2, hipStream_t stream) {
     const bool pair = p2 <= 127;
     if (npaths == 4) {
-        if (pair) launch_fused_t<EPL, 4, true>(one, wl, stream);
-        else launch_fused_t<EPL, 4, false>(one, wl, stream);
+        if (pair) launch_fused_t<EPL, 4, true, FINE>(one, wl, stream);
+        else launch_fused_t<EPL, 4, false, FINE>(one, wl, stream);
     } else {
-        if (pair) launch_fused_t<EPL, 8, true>(one, wl, stream);
-        else launch_fused_t<EPL, 8, false>(one, wl, stream);
+        if (pair) launch_fused_t<EPL, 8, true, FINE>(one, wl, stream);
+        else launch_fused_t<EPL, 8, false, FINE>(one, wl, stream);
     }
 }
 
+template <bool FINE>
 void launch_fused_any(const Frame* one, const WorkList* wl, int ndisp, int npaths, int p2,
                       hipStream_t stream) {
-    if (ndisp <= 64) launch_fused_epl<1>(one, wl, npaths, p2, stream);
-    else if (ndisp <= 128) launch_fused_epl<2>(one, wl, npaths, p2, stream);
-    else launch_fused_epl<4>(one, wl, npaths, p2, stream);
+    if (ndisp <= 64) launch_fused_epl<1, FINE>(one, wl, npaths, p2, stream);
+    else if (ndisp <= 128) launch_fused_epl<2, FINE>(one, wl, npaths, p2, stream);
+    else launch_fused_epl<4, FINE>(one, wl, npaths, p2, stream);
+}
+
+// ---- subpixel output: LR check on the integer maps, then the median over
+// the refined values (pixels outside the image and invalid pixels count as
+// +inf; a median of +inf is invalid).  Invalid pixels are -1.0f.
+constexpr float kInvalidF = -1.0f;
+
+struct MedianTileF {
+    float v[(kTH + 2) * (kTW + 2)];
+};
+
+__device__ __forceinline__ float median9f(float v[9]) {
+#pragma unroll
+    for (int pass = 0; pass < 5; ++pass) {
+#pragma unroll
+        for (int i = 0; i < 8 - pass; ++i) {
+            const float lo = fminf(v[i], v[i + 1]);
+            const float hi = fmaxf(v[i], v[i + 1]);
+            v[i] = lo;
+            v[i + 1] = hi;
+        }
+    }
+    return v[4];
+}
+
+__global__ __launch_bounds__(256) void check_median_fine_kernel(Frame f) {
+    __shared__ MedianTileF mt;
+    float* tile = mt.v;
+    const int width = f.width, height = f.height, tolerance = f.lr_tolerance;
+    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
+    for (int i = threadIdx.x; i < (kTH + 2) * (kTW + 2); i += 256) {
+        const int ly = i / (kTW + 2), lx = i - ly * (kTW + 2);
+        const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+        float v = INFINITY;
+        if (gx >= 0 && gx < width && gy >= 0 && gy < height) {
+            const size_t row = (size_t)gy * width;
+            const int dl = f.disp_left[row + gx];
+            bool ok = true;
+            if (tolerance >= 0) {
+                const int xr = gx - dl;
+                ok = false;
+                if (xr >= 0) {
+                    const int dr = (int)(f.right_keys[row + xr] & 0xFFu);
+                    const int diff = dl > dr ? dl - dr : dr - dl;
+                    ok = diff <= tolerance;
+                }
+            }
+            if (ok) v = f.fine_left[row + gx];
+        }
+        tile[i] = v;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & (kTW - 1), ty = threadIdx.x / kTW;
+    const int gx = x0 + tx, gy = y0 + ty;
+    if (gx < width && gy < height) {
+        const float* c = &tile[(ty + 1) * (kTW + 2) + tx + 1];
+        float out = *c;
+        if (f.median3x3 && out != INFINITY) {
+            float v[9];
+            int k = 0;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) v[k++] = c[dy * (kTW + 2) + dx];
+            out = median9f(v);
+        }
+        const size_t idx = (size_t)gy * width + gx;
+        f.disp_fine[idx] = out == INFINITY ? kInvalidF : out;
+        if (f.disp_right) f.disp_right[idx] = (uint16_t)(f.right_keys[idx] & 0xFFu);
+    }
 }
 
 }  // namespace
@@ -496,24 +675,39 @@ bool fused_select_supported(int ndisp, int npaths, int p2) {
     return ndisp % 16 == 0 && ndisp <= 256 && p2 <= 255 && (npaths == 4 || npaths == 8);
 }
 
-hipError_t launch_aggregate_select(const Frame& f, hipStream_t stream) {
+hipError_t launch_aggregate_select(const Frame& f, hipStream_t stream, bool fine) {
     hipError_t e = launch_paths(f, stream);
     if (e != hipSuccess) return e;
     const size_t n = (size_t)f.width * f.height;
     fill_keys_kernel<<<fill_blocks(n), 256, 0, stream>>>(f);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    launch_fused_any(&f, nullptr, f.ndisp, f.npaths, f.p2, stream);
+    if (fine) launch_fused_any<true>(&f, nullptr, f.ndisp, f.npaths, f.p2, stream);
+    else launch_fused_any<false>(&f, nullptr, f.ndisp, f.npaths, f.p2, stream);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 g2(median_blocks_x(f.width), (f.height + kTH - 1) / kTH);
-    check_median_kernel<<<g2, 256, 0, stream>>>(f);
+    if (fine) check_median_fine_kernel<<<g2, 256, 0, stream>>>(f);
+    else check_median_kernel<<<g2, 256, 0, stream>>>(f);
     return hipGetLastError();
 }
 
 hipError_t launch_select_fused_batch(const WorkList& wl, int ndisp, int npaths, int p2,
                                      hipStream_t stream) {
-    launch_fused_any(nullptr, &wl, ndisp, npaths, p2, stream);
+    launch_fused_any<false>(nullptr, &wl, ndisp, npaths, p2, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_wta_lrc_fine(const Frame& f, hipStream_t stream) {
+    const size_t n = (size_t)f.width * f.height;
+    fill_keys_kernel<<<fill_blocks(n), 256, 0, stream>>>(f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    launch_select_any<true>(&f, nullptr, f.ndisp, stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2(median_blocks_x(f.width), (f.height + kTH - 1) / kTH);
+    check_median_fine_kernel<<<g2, 256, 0, stream>>>(f);
     return hipGetLastError();
 }
 
@@ -522,11 +716,27 @@ hipError_t launch_wta_lrc(const Frame& f, hipStream_t stream) {
     fill_keys_kernel<<<fill_blocks(n), 256, 0, stream>>>(f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    launch_select_any(&f, nullptr, f.ndisp, stream);
+    launch_select_any<false>(&f, nullptr, f.ndisp, stream);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 g2(median_blocks_x(f.width), (f.height + kTH - 1) / kTH);
     check_median_kernel<<<g2, 256, 0, stream>>>(f);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_pair(const uint8_t* left, const uint8_t* right, int width, int height,
+                            int pitch, uint8_t* ref, uint8_t* mat, hipStream_t stream) {
+    const dim3 g((width + 255) / 256, height);
+    flip_pair_kernel<<<g, 256, 0, stream>>>(left, right, width, height, pitch, ref, mat);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_exact(const uint16_t* disp_left, const uint16_t* flipped, int width,
+                              int height, int tolerance, int median, uint16_t* disp,
+                              uint16_t* disp_right, hipStream_t stream) {
+    const dim3 g(median_blocks_x(width), (height + kTH - 1) / kTH);
+    check_median_exact_kernel<<<g, 256, 0, stream>>>(disp_left, flipped, width, height, tolerance,
+                                                      median, disp, disp_right);
     return hipGetLastError();
 }
 
@@ -536,7 +746,7 @@ hipError_t launch_fill_keys_batch(const WorkList& wl, hipStream_t stream) {
 }
 
 hipError_t launch_select_batch(const WorkList& wl, int ndisp, hipStream_t stream) {
-    launch_select_any(nullptr, &wl, ndisp, stream);
+    launch_select_any<false>(nullptr, &wl, ndisp, stream);
     return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ SGM_ERR_WORKSPACE = -5
 
 EXPORTS = ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_aggregate_work_bytes", "sgm_wta_lrc",
            "sgm_wta_lrc_work_elems", "sgm_aggregate_select", "sgm_aggregate_select_work_bytes",
+           "sgm_aggregate_select_subpixel", "sgm_aggregate_select_subpixel_work_bytes",
+           "sgm_disparity_exact_lr", "sgm_disparity_exact_lr_work_bytes",
            "sgm_batch_workspace_bytes", "sgm_batch_plan_create",
            "sgm_batch_run", "sgm_batch_frames", "sgm_batch_plan_destroy", "sgm_aggregate_variants",
            "sgm_status_string",
@@ -83,6 +85,15 @@ def load_library(path: str = LIB_PATH):
                                          ctypes.c_size_t, P]
     lib.sgm_aggregate_select_work_bytes.argtypes = [I32, I32, I32, I32, I32]
     lib.sgm_aggregate_select_work_bytes.restype = ctypes.c_size_t
+    lib.sgm_aggregate_select_subpixel.argtypes = lib.sgm_aggregate_select.argtypes
+    lib.sgm_aggregate_select_subpixel.restype = I32
+    lib.sgm_aggregate_select_subpixel_work_bytes.argtypes = [I32, I32, I32, I32, I32]
+    lib.sgm_aggregate_select_subpixel_work_bytes.restype = ctypes.c_size_t
+    lib.sgm_disparity_exact_lr.argtypes = [P, P, I32, I32, I32, I32, ctypes.POINTER(SgmParams), P, P,
+                                           P, ctypes.c_size_t, P]
+    lib.sgm_disparity_exact_lr.restype = I32
+    lib.sgm_disparity_exact_lr_work_bytes.argtypes = [I32, I32, I32, ctypes.POINTER(SgmParams)]
+    lib.sgm_disparity_exact_lr_work_bytes.restype = ctypes.c_size_t
     PP = ctypes.POINTER(SgmPair)
     lib.sgm_batch_workspace_bytes.argtypes = [PP, I32, ctypes.POINTER(SgmParams), ctypes.c_char_p]
     lib.sgm_batch_workspace_bytes.restype = ctypes.c_size_t
@@ -269,6 +280,39 @@ def sgm_aggregate_select(cost: torch.Tensor, npaths: int, p1: int, p2: int, lr_t
     return out, out_right
 
 
+def aggregate_select_subpixel_work_bytes(width: int, height: int, ndisp: int, npaths: int,
+                                         p2: int) -> int:
+    return int(load_library().sgm_aggregate_select_subpixel_work_bytes(width, height, ndisp,
+                                                                       npaths, p2))
+
+
+def sgm_aggregate_select_subpixel(cost: torch.Tensor, npaths: int, p1: int, p2: int,
+                                  lr_tolerance: int, median3x3: bool,
+                                  out: Optional[torch.Tensor] = None,
+                                  out_right: Optional[torch.Tensor] = None,
+                                  work: Optional[torch.Tensor] = None, want_right: bool = False,
+                                  stream=None):
+    """sgm_aggregate_select with subpixel refinement.  Returns (disp float32
+    [H][W] with -1.0 for invalid pixels, D^R uint16 or None)."""
+    if cost.dtype != torch.uint8 or cost.dim() != 3:
+        raise ValueError("cost must be a 3-D uint8 tensor")
+    h, w, nd = cost.shape
+    dev = cost.device
+    if out is None:
+        out = _empty((h, w), torch.float32, dev)
+    _expect(out, torch.float32, (h, w), "out")
+    if want_right and out_right is None:
+        out_right = _empty((h, w), torch.uint16, dev)
+    if out_right is not None:
+        _expect(out_right, torch.uint16, (h, w), "out_right")
+    if work is None:
+        work = _aligned_bytes(max(1, aggregate_select_subpixel_work_bytes(w, h, nd, npaths, p2)), dev)
+    _check(load_library().sgm_aggregate_select_subpixel(
+        _ptr(cost), w, h, nd, npaths, p1, p2, lr_tolerance, int(bool(median3x3)), _ptr(out),
+        _ptr(out_right), _ptr(work), work.numel(), _stream(stream)))
+    return out, out_right
+
+
 @dataclass(frozen=True)
 class Params:
     """Pipeline parameters (lr_tolerance < 0 skips the LR check)."""
@@ -326,6 +370,41 @@ class StereoSGM:
 
 def _params_struct(p: Params) -> SgmParams:
     return SgmParams(p.win_w, p.win_h, p.npaths, p.p1, p.p2, p.lr_tolerance, int(bool(p.median3x3)))
+
+
+def disparity_exact_lr_work_bytes(width: int, height: int, params: Params) -> int:
+    prm = _params_struct(params)
+    return int(load_library().sgm_disparity_exact_lr_work_bytes(width, height, params.ndisp,
+                                                                ctypes.byref(prm)))
+
+
+def sgm_disparity_exact_lr(left: torch.Tensor, right: torch.Tensor, params: Params,
+                           out: Optional[torch.Tensor] = None,
+                           out_right: Optional[torch.Tensor] = None,
+                           work: Optional[torch.Tensor] = None, want_right: bool = False,
+                           stream=None):
+    """The whole path with the exact consistency check (D^R matched from
+    scratch on the swapped, flipped pair).  left, right: uint8 [H][W] device
+    images.  Returns (disp, exact D^R or None), uint16 [H][W]."""
+    if left.dtype != torch.uint8 or left.dim() != 2 or right.shape != left.shape or \
+            right.dtype != torch.uint8:
+        raise ValueError("left and right must be uint8 [H][W] tensors of one shape")
+    h, w = left.shape
+    dev = left.device
+    if out is None:
+        out = _empty((h, w), torch.uint16, dev)
+    _expect(out, torch.uint16, (h, w), "out")
+    if want_right and out_right is None:
+        out_right = _empty((h, w), torch.uint16, dev)
+    if out_right is not None:
+        _expect(out_right, torch.uint16, (h, w), "out_right")
+    if work is None:
+        work = _aligned_bytes(max(1, disparity_exact_lr_work_bytes(w, h, params)), dev)
+    prm = _params_struct(params)
+    _check(load_library().sgm_disparity_exact_lr(_ptr(left), _ptr(right), w, h, w, params.ndisp,
+                                                 ctypes.byref(prm), _ptr(out), _ptr(out_right),
+                                                 _ptr(work), work.numel(), _stream(stream)))
+    return out, out_right
 
 
 class BatchPlan:

@@ -143,6 +143,32 @@ def test_aggregate_select_validation(lib):
     assert lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 7937) == 0
 
 
+def test_exact_lr_validation(lib):
+    f = lib.sgm_disparity_exact_lr
+    W = lambda v: ctypes.c_size_t(v)
+    prm = sgm.SgmParams(9, 7, 8, 10, 120, 1, 1)
+    R = ctypes.byref
+    big = 1 << 40
+    assert f(P(NULL), P(FAKE), 8, 8, 8, 16, R(prm), P(FAKE), P(NULL), P(FAKE), W(big), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 8, 8, 7, 16, R(prm), P(FAKE), P(NULL), P(FAKE), W(big), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 16, None, P(FAKE), P(NULL), P(FAKE), W(big), P(NULL)) == ARG
+    bad = sgm.SgmParams(3, 3, 8, 10, 120, 1, 1)
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 16, R(bad), P(FAKE), P(NULL), P(FAKE), W(big), P(NULL)) == UNSUP
+    bad = sgm.SgmParams(9, 7, 8, 121, 120, 1, 1)
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 16, R(bad), P(FAKE), P(NULL), P(FAKE), W(big), P(NULL)) == ARG
+    assert lib.sgm_disparity_exact_lr_work_bytes(8, 8, 16, R(bad)) == 0
+    need = lib.sgm_disparity_exact_lr_work_bytes(8, 8, 16, R(prm))
+    n = 64
+    # flipped pair, census x2, cost, the aggregation workspace, D^L and the flipped map
+    assert need == 2 * 256 + 2 * 512 + 1024 + lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 120) \
+        + 2 * 256
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 16, R(prm), P(FAKE), P(NULL), P(NULL), W(need), P(NULL)) == WS
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 16, R(prm), P(FAKE), P(NULL), P(FAKE), W(need - 1), P(NULL)) == WS
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 16, R(prm), P(FAKE), P(NULL), P(FAKE + 64), W(need), P(NULL)) == ALIGN
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 16, R(prm), P(FAKE + 2), P(NULL), P(FAKE), W(need), P(NULL)) == ALIGN
+    assert n == 64
+
+
 def test_python_binding_rejects_host_tensors(lib):
     import torch
     img = torch.zeros(4, 4, dtype=torch.uint8)
