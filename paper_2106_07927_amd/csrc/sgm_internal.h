@@ -200,15 +200,10 @@ __host__ __device__ inline int select_blocks_x(int w) {
     return (segs + kSelectWaves - 1) / kSelectWaves;
 }
 
-// row segment of one wave in the fused path-sum + selection pass
-#ifndef SGM_FUSED_SEG
-#define SGM_FUSED_SEG 128
-#endif
-constexpr int kFusedSeg = SGM_FUSED_SEG;
-__host__ __device__ inline int fused_blocks_x(int w) {
-    const int segs = (w + kFusedSeg - 1) / kFusedSeg;
-    return (segs + kSelectWaves - 1) / kSelectWaves;
-}
+// pixels of one row per block of the fused path-sum + selection pass
+constexpr int kFusedTile = 64;
+constexpr int kMaxFusedD = 256;
+__host__ __device__ inline int fused_blocks_x(int w) { return (w + kFusedTile - 1) / kFusedTile; }
 
 constexpr int kMedianTileW = 64;
 constexpr int kMedianTileH = 4;

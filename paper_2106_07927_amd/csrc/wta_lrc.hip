@@ -261,124 +261,111 @@ __device__ __forceinline__ void select_block(SelectTile<FINE>& st, const uint16_
 }
 
 // ---- path sum fused with the selection pass --------------------------------
-// The wave walks its segment in chunks of KP = 16 / EPL pixels, i.e. at most
-// 1024 volume elements: lane l sums the l-th 16-byte block of the chunk from
-// the cost volume and the NP uint8 penalty slices (merge16), parks the 16
-// sums in LDS, and then the chunk's pixels go through the same selection
-// steps as above, reading S_bar from LDS instead of HBM.  Loads run
-// kFusedPrefetch chunks ahead.  Needs D % 16 == 0, so every chunk starts on a
-// 16-byte boundary.
-constexpr int kFusedElems = 1024;
-#ifndef SGM_FUSED_PREFETCH
-#define SGM_FUSED_PREFETCH 2
-#endif
-constexpr int kFusedPrefetch = SGM_FUSED_PREFETCH;
-
-template <bool FINE>
-struct FusedTile {
-    SelectTile<FINE> sel;
-    uint16_t sbar[kSelectWaves][kFusedElems];
-};
-
-template <int NP>
-struct ChunkRaw {
-    uint4 c;
-    uint4 a[NP];
-};
-
-template <int EPL, int NP, bool PAIR, bool FINE>
-__device__ __forceinline__ void select_fused_block(FusedTile<FINE>& st, const Frame& f, int bx, int y) {
-    constexpr int KP = 16 / EPL;                   // pixels per chunk
-    const int wave = threadIdx.x >> 6;
+// A block owns a tile of kFusedTile pixels of one row.
+//  (1) Its threads sum the tile's 16-byte blocks of the cost volume and of the
+//      uint8 penalty slices (merge16) into an LDS copy of S_bar: one row of D
+//      values per pixel, padded by one dword so that rows start in different
+//      banks.  S_bar never goes to HBM.
+//  (2) Four threads per pixel take the minimum key (S_bar << 8) | d over a
+//      quarter of the disparities each; a quad reduction gives D^L (and with
+//      FINE the refined value, from the winner's two neighbours in LDS).
+//  (3) One thread per right-view pixel q folds key(q + d, d) over the d with
+//      q + d inside the tile and merges that partial minimum into the D^R key
+//      map with atomicMin; the tiles holding q .. q + D - 1 complete it.
+// Needs D % 16 == 0, so every 16-byte block lies inside one pixel's vector.
+template <int NP, bool PAIR, bool FINE>
+__device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, const Frame& f, int bx,
+                                                  int y) {
     const int width = f.width, ndisp = f.ndisp;
-    const int x0 = (bx * kSelectWaves + wave) * kFusedSeg;
-    if (x0 >= width) return;                       // uniform per wave
-    const int x1 = min(width, x0 + kFusedSeg);
-    SelectWave<EPL, FINE> sw;
-    sw.init(st.sel.key[wave], f.disp_left, f.fine_left, f.right_keys, width, ndisp, y, x0, x1);
-    uint16_t* sb = st.sbar[wave];
-    const int lane = sw.lane;
+    const int x0 = bx * kFusedTile;
+    const int npx = min(kFusedTile, width - x0);
+    const int rs = ndisp + 2;                      // LDS row stride (uint16)
+    const size_t row = (size_t)y * width;
+    const uint32_t e_tile = (uint32_t)(row + x0) * (uint32_t)ndisp;
+    const uint32_t e_last = (uint32_t)(row + x0 + npx) * (uint32_t)ndisp - 16u;
 
-    // element offsets: this lane's block of chunk c, clamped to the segment's
-    // last block (chunks past the end and idle lanes re-read it)
-    const uint32_t seg_e0 = (uint32_t)(sw.row + x0) * (uint32_t)ndisp;
-    const uint32_t last_blk = (uint32_t)(sw.row + x1) * (uint32_t)ndisp - 16u;
-    const uint8_t* slice[NP];
+    // (1) path sum into LDS; blocks past the row's last pixel re-read its
+    // last block and land in LDS rows that are never read
+    const int nblk = kFusedTile * ndisp / 16;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        const uint32_t e = min(e_tile + 16u * (uint32_t)b, e_last);
+        const uint4 c = *reinterpret_cast<const uint4*>(f.cost + e);
+        uint4 a[NP];
 #pragma unroll
-    for (int r = 0; r < NP; ++r) slice[r] = f.slices + (size_t)r * f.slice_stride;
-    auto fetch = [&](int c) {
-        const uint32_t e = min(seg_e0 + (uint32_t)(c * KP * ndisp) + 16u * (uint32_t)lane, last_blk);
-        ChunkRaw<NP> raw;
-        raw.c = *reinterpret_cast<const uint4*>(f.cost + e);
+        for (int r = 0; r < NP; ++r)
+            a[r] = *reinterpret_cast<const uint4*>(f.slices + (size_t)r * f.slice_stride + e);
+        uint32_t sum[8];
+        merge16<NP, PAIR>(c, a, sum);
+        const int p = (16 * b) / ndisp;
+        const int d = 16 * b - p * ndisp;
+        uint32_t* dst = reinterpret_cast<uint32_t*>(sb + p * rs + d);
 #pragma unroll
-        for (int r = 0; r < NP; ++r) raw.a[r] = *reinterpret_cast<const uint4*>(slice[r] + e);
-        return raw;
-    };
-    const int d0c = sw.d0 < ndisp ? sw.d0 : 0;
-    auto chunk = [&](const ChunkRaw<NP>& raw, int c) {
-        uint32_t s[8];
-        merge16<NP, PAIR>(raw.c, raw.a, s);
-        uint4* dst = reinterpret_cast<uint4*>(sb + 16 * lane);
-        dst[0] = make_uint4(s[0], s[1], s[2], s[3]);
-        dst[1] = make_uint4(s[4], s[5], s[6], s[7]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int xc = x0 + c * KP;
-#pragma unroll
-        for (int j = 0; j < KP; ++j) {
-            const int x = xc + j;
-            if (x < x1) {                          // uniform
-                RawVals<EPL> cv;
-                const uint16_t* p = sb + j * ndisp + d0c;
-                if constexpr (EPL == 1) cv.w[0] = *p;
-                else if constexpr (EPL == 2) cv.w[0] = *reinterpret_cast<const uint32_t*>(p);
-                else {
-                    const uint2 w = *reinterpret_cast<const uint2*>(p);
-                    cv.w[0] = w.x;
-                    cv.w[1] = w.y;
-                }
-                sw.step(cv, x);
+        for (int k = 0; k < 8; ++k) dst[k] = sum[k];
+    }
+    __syncthreads();
+
+    // (2) D^L: quad (p, part) covers disparities part * D/4 .. (part+1) * D/4 - 1
+    {
+        const int p = threadIdx.x >> 2, part = threadIdx.x & 3;
+        const int dq = ndisp >> 2;
+        uint32_t best = kInf;
+        if (p < npx) {
+            const uint16_t* src = sb + p * rs + part * dq;
+            for (int i = 0; i < dq; i += 2) {
+                const uint32_t w = *reinterpret_cast<const uint32_t*>(src + i);
+                const uint32_t d = (uint32_t)(part * dq + i);
+                best = min(best, min(((w & 0xFFFFu) << 8) | d, ((w >> 16) << 8) | (d + 1)));
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    };
-
-    const int nch = (x1 - x0 + KP - 1) / KP;
-    ChunkRaw<NP> ring[kFusedPrefetch];
-#pragma unroll
-    for (int p = 0; p < kFusedPrefetch; ++p) ring[p] = fetch(p);
-    for (int c0 = 0; c0 < nch; c0 += kFusedPrefetch) {
-#pragma unroll
-        for (int p = 0; p < kFusedPrefetch; ++p) {
-            const int c = c0 + p;
-            if (c < nch) {                         // uniform
-                const ChunkRaw<NP> raw = ring[p];
-                ring[p] = fetch(c + kFusedPrefetch);
-                chunk(raw, c);
+        best = min(best, dpp<kDppQuadSwap1>(kInf, best));
+        best = min(best, dpp<kDppQuadSwap2>(kInf, best));
+        if (part == 0 && p < npx) {
+            const int d = (int)(best & 0xFFu);
+            f.disp_left[row + x0 + p] = (uint16_t)d;
+            if constexpr (FINE) {
+                float v = (float)d;
+                if (d > 0 && d < ndisp - 1)
+                    v = refine(d, sb[p * rs + d - 1], best >> 8, sb[p * rs + d + 1]);
+                f.fine_left[row + x0 + p] = v;
             }
         }
     }
-    sw.finish();
+
+    // (3) D^R partial minima: q = x0 - D + 1 + t; tile pixel k holds d = k + x0 - q
+    const int nq = npx + ndisp - 1;
+    for (int t = threadIdx.x; t < nq; t += blockDim.x) {
+        const int q = x0 - ndisp + 1 + t;
+        const int off = x0 - q;                    // d of tile pixel 0
+        uint32_t best = kInf;
+        const int k0 = max(0, -off), k1 = min(npx, ndisp - off);
+        const uint16_t* src = sb + k0 * (rs + 1) + off;
+        for (int k = k0; k < k1; ++k, src += rs + 1)
+            best = min(best, ((uint32_t)*src << 8) | (uint32_t)(k + off));
+        if (q >= 0) atomicMin(&f.right_keys[row + q], best);
+    }
+    __syncthreads();   // the LDS tile is reused by the next work item
 }
 
-template <int EPL, int NP, bool PAIR, bool FINE>
-__global__ __launch_bounds__(64 * kSelectWaves) void select_fused_kernel(Frame f) {
-    __shared__ FusedTile<FINE> st;
-    select_fused_block<EPL, NP, PAIR, FINE>(st, f, blockIdx.x, blockIdx.y);
+// LDS of the fused pass: kFusedTile rows of D + 2 values, sized at launch
+__host__ __device__ inline size_t fused_lds_bytes(int ndisp) {
+    return (size_t)kFusedTile * (size_t)(ndisp + 2) * sizeof(uint16_t);
 }
 
-template <int EPL, int NP, bool PAIR>
-__global__ __launch_bounds__(64 * kSelectWaves) void select_fused_batch_kernel(WorkList wl) {
-    __shared__ FusedTile<false> st;
+template <int NP, bool PAIR, bool FINE>
+__global__ __launch_bounds__(256) void select_fused_kernel(Frame f) {
+    extern __shared__ uint16_t sb[];
+    select_tile_block<NP, PAIR, FINE>(sb, f, blockIdx.x, blockIdx.y);
+}
+
+template <int NP, bool PAIR>
+__global__ __launch_bounds__(256) void select_fused_batch_kernel(WorkList wl) {
+    extern __shared__ uint16_t sb[];
     for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
         const int fi = find_frame(wl, b);
         const Frame& f = wl.frames[fi];
         const int lb = b - wl.starts[fi];
         const int bxs = fused_blocks_x(f.width);
-        select_fused_block<EPL, NP, PAIR, false>(st, f, lb % bxs, lb / bxs);
+        select_tile_block<NP, PAIR, false>(sb, f, lb % bxs, lb / bxs);
     }
 }
 
@@ -568,35 +555,29 @@ void launch_select_any(const Frame* one, const WorkList* wl, int ndisp, hipStrea
     }
 }
 
-template <int EPL, int NP, bool PAIR, bool FINE>
-void launch_fused_t(const Frame* one, const WorkList* wl, hipStream_t stream) {
+template <int NP, bool PAIR, bool FINE>
+void launch_fused_t(const Frame* one, const WorkList* wl, int ndisp, hipStream_t stream) {
+    const size_t lds = fused_lds_bytes(ndisp);
     if (one) {
         const dim3 g(fused_blocks_x(one->width), one->height);
-        select_fused_kernel<EPL, NP, PAIR, FINE><<<g, 64 * kSelectWaves, 0, stream>>>(*one);
+        select_fused_kernel<NP, PAIR, FINE><<<g, 256, lds, stream>>>(*one);
     } else {
-        select_fused_batch_kernel<EPL, NP, PAIR>
-            <<<persistent_grid(wl->total, 2), 64 * kSelectWaves, 0, stream>>>(*wl);
+        select_fused_batch_kernel<NP, PAIR><<<persistent_grid(wl->total), 256, lds, stream>>>(*wl);
     }
 }
 
-template <int EPL, bool FINE>
-void launch_fused_epl(const Frame* one, const WorkList* wl, int npaths, int p2, hipStream_t stream) {
-    const bool pair = p2 <= 127;
-    if (npaths == 4) {
-        if (pair) launch_fused_t<EPL, 4, true, FINE>(one, wl, stream);
-        else launch_fused_t<EPL, 4, false, FINE>(one, wl, stream);
-    } else {
-        if (pair) launch_fused_t<EPL, 8, true, FINE>(one, wl, stream);
-        else launch_fused_t<EPL, 8, false, FINE>(one, wl, stream);
-    }
-}
-
+// frames of one launch share D (the LDS size depends on it)
 template <bool FINE>
 void launch_fused_any(const Frame* one, const WorkList* wl, int ndisp, int npaths, int p2,
                       hipStream_t stream) {
-    if (ndisp <= 64) launch_fused_epl<1, FINE>(one, wl, npaths, p2, stream);
-    else if (ndisp <= 128) launch_fused_epl<2, FINE>(one, wl, npaths, p2, stream);
-    else launch_fused_epl<4, FINE>(one, wl, npaths, p2, stream);
+    const bool pair = p2 <= 127;
+    if (npaths == 4) {
+        if (pair) launch_fused_t<4, true, FINE>(one, wl, ndisp, stream);
+        else launch_fused_t<4, false, FINE>(one, wl, ndisp, stream);
+    } else {
+        if (pair) launch_fused_t<8, true, FINE>(one, wl, ndisp, stream);
+        else launch_fused_t<8, false, FINE>(one, wl, ndisp, stream);
+    }
 }
 
 // ---- subpixel output: LR check on the integer maps, then the median over
