@@ -234,7 +234,8 @@ size_t sgm_batch_workspace_bytes(const sgm_pair* pairs, int32_t n,
  * captures the whole batch into a hipGraph on a stream of its own.
  * tune_table: NULL, or a JSON object mapping "WxHxD" to the path-kernel
  * lane-layout variant to use for pairs of that shape (written by the
- * project's tuner; unknown shapes use variant 0).  Variants never change
+ * project's tuner; other shapes use the library's default for their size,
+ * as the single-frame calls do).  Variants never change
  * results.
  * Errors: SGM_ERR_ARG, SGM_ERR_WORKSPACE, SGM_ERR_ALIGN, SGM_ERR_HIP.
  */

@@ -46,6 +46,23 @@ constexpr int kThreads = 64 * kWaves;
 
 enum Kind : int { kHorizontal = 0, kVertical = 1, kDiagonal = 2 };
 
+// Steps per chunk of the path loop, by lane layout (horizontal lines with one
+// / more packed registers per lane, other lines with <= 4 / 8 registers).
+#ifndef SGM_STEPS_H1
+#define SGM_STEPS_H1 32
+#endif
+#ifndef SGM_STEPS_H2
+#define SGM_STEPS_H2 16
+#endif
+#ifndef SGM_STEPS_O4
+#define SGM_STEPS_O4 16
+#endif
+#ifndef SGM_STEPS_O8
+#define SGM_STEPS_O8 8
+#endif
+constexpr int kStepsH1 = SGM_STEPS_H1, kStepsH2 = SGM_STEPS_H2;
+constexpr int kStepsO4 = SGM_STEPS_O4, kStepsO8 = SGM_STEPS_O8;
+
 struct DirTask {
     int dx, dy;      // step r: the predecessor of p is p - r
     int nlines;      // independent lines of this direction
@@ -331,8 +348,8 @@ template <int NH, int LH, int NO, int LO, bool ALH, bool PDH, bool ALO, bool PDO
 __device__ __forceinline__ void paths_block(const Frame& f, int lb) {
     // steps per chunk: enough to cover a memory round trip, few enough to
     // keep two chunks of cost bytes in registers
-    constexpr int KH = NH == 1 ? 32 : 16;
-    constexpr int KO = NO <= 4 ? 16 : 8;
+    constexpr int KH = NH == 1 ? kStepsH1 : kStepsH2;
+    constexpr int KO = NO <= 4 ? kStepsO4 : kStepsO8;
     int block0, di;
     const DirTask task = find_dir(lb, f.width, f.height, f.npaths, LH, LO, &block0, &di);
     const int wave_in_dir = (lb - block0) * kWaves + (int)(threadIdx.x >> 6);
@@ -529,6 +546,17 @@ PathLayout path_layout(int ndisp, int variant) {
     return variant == 1 ? PathLayout{4, 32, 8, 16} : PathLayout{2, 64, 8, 16};
 }
 
+// Variant used when none is asked for (variant < 0): the layout the tuner
+// measured fastest for frames of this size class.  Large frames have enough
+// horizontal lines to trade per-step latency for fewer instructions.
+int default_variant(int width, int height, int ndisp) {
+    const long px = (long)width * height;
+    if (ndisp <= 32 || ndisp > 128) return 0;
+    if (px >= 1500000) return 1;
+    if (ndisp > 64 && px >= 400000) return 2;
+    return 0;
+}
+
 int path_blocks(int width, int height, int ndisp, int npaths, int variant) {
     const PathLayout l = path_layout(ndisp, variant);
     int nb = 0;
@@ -547,7 +575,9 @@ size_t aggregate_work_bytes(int width, int height, int ndisp, int npaths, int p2
 }
 
 hipError_t launch_paths(const Frame& f, hipStream_t stream) {
-    const int variant = (f.variant >= 0 && f.variant < path_variants(f.ndisp)) ? f.variant : 0;
+    const int variant = (f.variant >= 0 && f.variant < path_variants(f.ndisp))
+                            ? f.variant
+                            : default_variant(f.width, f.height, f.ndisp);
     const int nb = path_blocks(f.width, f.height, f.ndisp, f.npaths, variant);
     return launch_paths_any(&f, nullptr, f.ndisp, variant, f.p2 <= 255, nb, stream);
 }

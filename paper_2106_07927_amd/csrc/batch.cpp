@@ -143,7 +143,8 @@ size_t build_layout(const sgm_pair* pairs, int32_t n, const sgm_params* p, const
         f.lr_tolerance = p->lr_tolerance;
         f.median3x3 = p->median3x3;
         const int tv = tuned_variant(tune_table, q.width, q.height, q.ndisp);
-        f.variant = (tv >= 0 && tv < path_variants(q.ndisp)) ? tv : 0;
+        f.variant = (tv >= 0 && tv < path_variants(q.ndisp)) ? tv
+                                                             : default_variant(q.width, q.height, q.ndisp);
         f.left = q.left;
         f.right = q.right;
         f.disp = q.disp_out;

@@ -3,9 +3,9 @@
 //
 // A 256-thread workgroup owns a 64 x 16 output tile.  The tile plus its
 // (RX, RY) halo is staged once through LDS with the zero margin applied at the
-// image border; every thread then computes four pixels, one column and four
-// rows apart, reading the window from LDS.  Output: one uint64 per pixel,
-// written coalesced along x.
+// image border; every thread then computes four consecutive pixels of one row
+// with packed byte compares (four comparisons per instruction group).
+// Output: one uint64 per pixel, written coalesced along x.
 #include "sgm_internal.h"
 
 namespace sgm {
@@ -18,10 +18,26 @@ struct CensusTile {
     static constexpr int LW = kCensusTileW + 2 * RX;
     static constexpr int LH = kCensusTileH + 2 * RY;
     static constexpr int LWP = (LW + 3) & ~3;
-    uint8_t px[LH * LWP];
+    alignas(16) uint8_t px[LH * LWP];          // rows start on dword boundaries
 };
 
-// Tile (bx, by) of one image.  Every thread passes the same barriers.
+// Unsigned per-byte a < b for four byte pairs at once, result in bit 7 of
+// every byte: with t = (a | 0x80) - (b & 0x7F) per byte (never borrows out of
+// the byte), a < b iff (a7 < b7) or (a7 == b7 and bit 7 of t is clear).  One
+// v_bitop3 evaluates that; its table is f(0xF0, 0xCC, 0xAA) for inputs
+// (a, b, t).
+__device__ __forceinline__ uint32_t bytes_less(uint32_t a, uint32_t b_low7, uint32_t b) {
+    const uint32_t t = (a | 0x80808080u) - b_low7;
+    return __builtin_amdgcn_bitop3_b32(a, b, t, 0x4D);
+}
+
+// Tile (bx, by) of one image.  Every thread passes the same barriers.  A
+// thread owns four consecutive pixels of one tile row: for every window
+// offset it compares the four neighbour bytes against the four centres at
+// once (bytes_less) and files the four result bits into per-pixel bytes, so
+// that after all offsets byte j of acc[g] holds bits 8g .. 8g+7 of pixel j's
+// descriptor (counted from the top of a 64-bit word whose leading unused bits
+// are zero); a byte transpose then gives each pixel its uint64.
 template <int RX, int RY>
 __device__ __forceinline__ void census_tile(CensusTile<RX, RY>& t, const uint8_t* __restrict__ img,
                                             int width, int height, int pitch,
@@ -38,36 +54,56 @@ __device__ __forceinline__ void census_tile(CensusTile<RX, RY>& t, const uint8_t
     }
     __syncthreads();
 
-    const int tx = threadIdx.x & (kCensusTileW - 1);
-    const int ty0 = threadIdx.x / kCensusTileW;
-    const int gx = x0 + tx;
-    if (gx < width) {
+    constexpr int kBits = (2 * RX + 1) * (2 * RY + 1) - 1;
+    constexpr int kLead = 64 - kBits;                  // unused top bits of the uint64
+    constexpr int kWords = (4 + 2 * RX + 3) / 4;       // dwords covering a quad's window row
+    const int q = threadIdx.x & 15;                    // quad of the tile row
+    const int ty = threadIdx.x >> 4;                   // tile row
+    const int gy = y0 + ty;
+    const int gx = x0 + 4 * q;
+    uint32_t acc[8];
 #pragma unroll
-        for (int r = 0; r < kCensusTileH / (kThreads / kCensusTileW); ++r) {
-            const int ty = ty0 + r * (kThreads / kCensusTileW);
-            const int gy = y0 + ty;
-            if (gy < height) {
-                const uint8_t* c = &t.px[(ty + RY) * T::LWP + tx + RX];
-                const uint32_t centre = *c;
-                // bits shifted in raster order: the first neighbour ends highest
-                uint32_t hi = 0, lo = 0;
-                int n = 0;
-                constexpr int kBits = (2 * RX + 1) * (2 * RY + 1) - 1;
-                constexpr int kHiBits = kBits > 32 ? kBits - 32 : 0;
+    for (int g = 0; g < 8; ++g) acc[g] = 0;
+    // the centres: columns 4q + RX .. 4q + RX + 3 of LDS row ty + RY
+    const uint32_t* crow = reinterpret_cast<const uint32_t*>(&t.px[(ty + RY) * T::LWP + 4 * q]);
+    const uint32_t centre = __builtin_amdgcn_alignbyte(crow[RX / 4 + 1], crow[RX / 4], RX % 4);
+    const uint32_t centre_low7 = centre & 0x7F7F7F7Fu;
+    int n = 0;
 #pragma unroll
-                for (int dy = -RY; dy <= RY; ++dy) {
+    for (int dy = -RY; dy <= RY; ++dy) {
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(&t.px[(ty + RY + dy) * T::LWP + 4 * q]);
+        uint32_t w[kWords + 1];
 #pragma unroll
-                    for (int dx = -RX; dx <= RX; ++dx) {
-                        if (dx == 0 && dy == 0) continue;
-                        const uint32_t bit = (uint32_t)c[dy * T::LWP + dx] < centre ? 1u : 0u;
-                        if (n < kHiBits) hi = (hi << 1) | bit;
-                        else lo = (lo << 1) | bit;
-                        ++n;
-                    }
-                }
-                out[(size_t)gy * width + gx] = ((uint64_t)hi << 32) | lo;
-            }
+        for (int k = 0; k < kWords; ++k) w[k] = row[k];
+        w[kWords] = 0;
+#pragma unroll
+        for (int dx = -RX; dx <= RX; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            const int c = RX + dx;                     // first column of the four neighbours
+            const uint32_t nb = __builtin_amdgcn_alignbyte(w[c / 4 + 1], w[c / 4], c % 4);
+            const uint32_t lt = bytes_less(nb, centre_low7, centre);
+            const int pos = kLead + n;                 // bit index from the top
+            const int sh = pos & 7;
+            acc[pos >> 3] |= (lt >> sh) & (0x80808080u >> sh);
+            ++n;
         }
+    }
+    // byte transpose: pixel j takes byte j of acc[0..7] (acc[0] the top byte)
+    uint64_t d[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t hi = 0, lo = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) hi |= ((acc[g] >> (8 * j)) & 0xFFu) << (8 * (3 - g));
+#pragma unroll
+        for (int g = 4; g < 8; ++g) lo |= ((acc[g] >> (8 * j)) & 0xFFu) << (8 * (7 - g));
+        d[j] = ((uint64_t)hi << 32) | lo;
+    }
+    if (gy < height) {
+        uint64_t* o = out + (size_t)gy * width + gx;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (gx + j < width) o[j] = d[j];
     }
     __syncthreads();   // the tile is reused by the next work item
 }

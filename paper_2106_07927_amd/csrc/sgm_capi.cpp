@@ -178,7 +178,7 @@ int32_t sgm_aggregate(const uint8_t* cost, int32_t width, int32_t height, int32_
     f.npaths = npaths;
     f.p1 = p1;
     f.p2 = p2;
-    f.variant = 0;
+    f.variant = -1;
     f.cost = const_cast<uint8_t*>(cost);
     f.slices = static_cast<uint8_t*>(work);
     f.slice_stride = sgm::aggregate_slice_elems(width, height, ndisp);
@@ -247,7 +247,7 @@ int32_t sgm_aggregate_select(const uint8_t* cost, int32_t width, int32_t height,
     f.p2 = p2;
     f.lr_tolerance = lr_tolerance;
     f.median3x3 = median3x3;
-    f.variant = 0;
+    f.variant = -1;
     f.cost = const_cast<uint8_t*>(cost);
     f.slices = reinterpret_cast<uint8_t*>(base);
     f.slice_stride = sgm::aggregate_slice_elems(width, height, ndisp);
@@ -290,7 +290,7 @@ int32_t sgm_aggregate_select_subpixel(const uint8_t* cost, int32_t width, int32_
     f.p2 = p2;
     f.lr_tolerance = lr_tolerance;
     f.median3x3 = median3x3;
-    f.variant = 0;
+    f.variant = -1;
     f.cost = const_cast<uint8_t*>(cost);
     f.slices = reinterpret_cast<uint8_t*>(base);
     f.slice_stride = sgm::aggregate_slice_elems(width, height, ndisp);
@@ -337,7 +337,7 @@ int32_t sgm_disparity_exact_lr(const uint8_t* left, const uint8_t* right, int32_
     f.npaths = params->npaths;
     f.p1 = params->p1;
     f.p2 = params->p2;
-    f.variant = 0;
+    f.variant = -1;
     f.census_left = reinterpret_cast<uint64_t*>(base + l.census_left);
     f.census_right = reinterpret_cast<uint64_t*>(base + l.census_right);
     f.cost = reinterpret_cast<uint8_t*>(base + l.cost);

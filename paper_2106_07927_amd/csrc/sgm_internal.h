@@ -138,7 +138,7 @@ __device__ __forceinline__ uint32_t group_prev(uint32_t v, uint32_t edge, bool f
 struct Frame {
     int32_t width, height, ndisp, pitch;
     int32_t win_w, win_h, npaths, p1, p2, lr_tolerance, median3x3;
-    int32_t variant;                 // lane-layout variant of the path kernel
+    int32_t variant;                 // lane-layout variant of the path kernel (< 0: default)
     const uint8_t* left;
     const uint8_t* right;
     uint64_t* census_left;
@@ -224,6 +224,7 @@ struct PathLayout {
     int nreg_o, lpl_o;    // vertical and diagonal lines
 };
 int path_variants(int ndisp);                       // number of variants (>= 1)
+int default_variant(int width, int height, int ndisp);
 PathLayout path_layout(int ndisp, int variant);
 int path_blocks(int width, int height, int ndisp, int npaths, int variant);
 size_t aggregate_slice_elems(int width, int height, int ndisp);
