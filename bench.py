@@ -52,11 +52,14 @@ def parse():
 
 
 # HBM bytes per call at the 1242x375 / D=128 / 8-path frame, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs of this script (profiles/hbm_traffic_*), each
+# FETCH_SIZE and WRITE_SIZE runs of this script (profiles/hbm_traffic_1242x375_d128_r8.md), each
 # scaled by what the same counter reads for a plain copy of known size.  An
 # entry holds only for the kernel sources whose digest it names; for any other
 # sources the figure is reported as null.
-TRAFFIC = {}
+TRAFFIC = {
+    "sgm_aggregate_select": {"sources": "ec75dfd9ef27003c", "bytes": 1488296733},
+    "sgm_aggregate": {"sources": "ec75dfd9ef27003c", "bytes": 1586737376},
+}
 
 KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "wta_lrc.hip", "sgm_internal.h")
 
