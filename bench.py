@@ -177,6 +177,61 @@ def served_form(args, torch, sgm, datagen):
             "plain_fifo": fifo.summary(specs)}
 
 
+def other_forms(args, torch, sgm, eng, left, right, prm, stream, des):
+    """The same frame through the subpixel form (the paper's "fine") and the
+    exact consistency check ("exact-cc"), timed like the main path."""
+    reps = max(1, min(50, args.steps))
+    fine_work = sgm._aligned_bytes(sgm.aggregate_select_subpixel_work_bytes(
+        eng.width, eng.height, prm.ndisp, prm.npaths, prm.p2), left.device)
+    fine_out = torch.empty((eng.height, eng.width), dtype=torch.float32, device=left.device)
+    exact_work = sgm._aligned_bytes(sgm.disparity_exact_lr_work_bytes(eng.width, eng.height, prm),
+                                    left.device)
+
+    def fine():
+        sgm.sgm_census(left, prm.win_w, prm.win_h, out=eng.census_left)
+        sgm.sgm_census(right, prm.win_w, prm.win_h, out=eng.census_right)
+        sgm.sgm_cost(eng.census_left, eng.census_right, prm.ndisp, out=eng.cost)
+        sgm.sgm_aggregate_select_subpixel(eng.cost, prm.npaths, prm.p1, prm.p2, prm.lr_tolerance,
+                                          prm.median3x3, out=fine_out, work=fine_work)
+
+    def exact():
+        sgm.sgm_disparity_exact_lr(left, right, prm, out=eng.disp, work=exact_work)
+
+    # NCC cost (the paper's KITTI penalties for it: P1 = 90, P2 = 880, which
+    # take the uint16 path slices and the unfused selection)
+    ncc_work = sgm._aligned_bytes(sgm.aggregate_select_work_bytes(
+        eng.width, eng.height, prm.ndisp, prm.npaths, 880), left.device)
+
+    def ncc(win):
+        def run():
+            sgm.sgm_cost_ncc(left, right, win, prm.ndisp, out=eng.cost)
+            sgm.sgm_aggregate_select(eng.cost, prm.npaths, 90, 880, prm.lr_tolerance,
+                                     prm.median3x3, out=eng.disp, work=ncc_work)
+        return run
+
+    out = {}
+    for name, fn in (("subpixel", fine), ("exact_lr_check", exact), ("ncc5x5", ncc(5)),
+                     ("ncc9x9", ncc(9))):
+        for _ in range(3):
+            fn()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(reps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        out[name] = {"ms_per_step": round(ms, 5), "value": round(des / (ms * 1e-3) / 1e6, 1),
+                     "unit": "MDE/s"}
+    out["paper_context"] = {"subpixel": 633.1, "exact_lr_check": 361.8, "ncc5x5": 442.4,
+                            "ncc9x9": 344.1, "unit": "MDE/s", "hardware": "Jetson AGX Xavier",
+                            "config": "8-path SGM, LR check + median (CT9x7 for subpixel "
+                                      "and exact_lr_check)"}
+    return out
+
+
 def cpu_baseline(pair, cfg, frames):
     import oracle
     prm = oracle.Params(win_w=cfg["win_w"], win_h=cfg["win_h"], ndisp=cfg["ndisp"],
@@ -217,8 +272,9 @@ def main():
         copy_probe(torch, dev, args.copy_probe_mib)
 
     def timed(fused):
-        """K steps of the whole path (after W warm-up steps); events on the
-        launch stream bracket every stage of every step."""
+        """K timed steps of the whole path after W warm-up steps, bracketed
+        by two events on the launch stream; then K more steps with events at
+        every stage boundary for the per-stage times and percentiles."""
         eng = sgm.StereoSGM(w, h, prm, device=dev, fused=fused)
         names = ("census", "cost", "aggregate_select") if fused else \
             ("census", "cost", "aggregate", "wta_lrc")
@@ -246,16 +302,20 @@ def main():
 
         for _ in range(args.warmup):
             step()
-        torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-               for _ in range(args.steps)]
         t_start = torch.cuda.Event(enable_timing=True)
         t_end = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t_start.record(stream)
+        for _ in range(args.steps):
+            step()
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        # a second pass of K steps with events at every stage boundary, for
+        # the stage breakdown and the per-step percentiles
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+               for _ in range(args.steps)]
         for i in range(args.steps):
             step(evs[i])
-        t_end.record(stream)
         torch.cuda.synchronize()
         per_step = sorted(e[0].elapsed_time(e[-1]) for e in evs)
         stages = {nm: sum(e[a].elapsed_time(e[a + 1]) for e in evs) / args.steps
@@ -298,6 +358,7 @@ def main():
     torch.cuda.synchronize()
     e2e_ms = (time.perf_counter() - t0) * 1e3 / e2e_n
     digest = sources_digest()
+    forms = other_forms(args, torch, sgm, eng, left, right, prm, stream, des)
 
     out = {
         "metric": METRIC,
@@ -339,6 +400,7 @@ def main():
                           "kernel": "sgm_aggregate (paths_kernel + merge_kernel)",
                           "algorithmic_bytes": agg_bytes}},
         "e2e_pcie_ms_per_frame": round(e2e_ms, 4),
+        "other_forms": forms,
         "paper_context": {"value": 644.9, "unit": "MDE/s",
                           "hardware": "Jetson AGX Xavier, 512-core Volta GPU",
                           "config": "CT9x7, 8-path SGM, LR check + median, incl. transfers"},

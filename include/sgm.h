@@ -83,6 +83,29 @@ int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right,
                  uint8_t* cost_out, void* stream);
 
 /*
+ * Inverted, truncated normalised cross-correlation cost (Sec. 2.1.1,
+ * Sec. 2.2.1), an alternative to sgm_census + sgm_cost:
+ *   s = 1 - max(0, Phi_NCC) over win x win patches centred on (x, y) in the
+ *   left image and (x - d, y) in the right image, with
+ *   Phi = (n S_LR - S_L S_R) / (sqrt(n S_LL - S_L^2) * sqrt(n S_RR - S_R^2)),
+ *   n = win^2 and S_* the integer sums over the two patches.
+ *   Stored as round(255 s) (ties to even) in the same uint8 volume as
+ *   sgm_cost, so the aggregation and selection calls apply unchanged.
+ *   Pixels outside the image read as zero; a patch without variance gives
+ *   cost 255, as does x - d < 0.  The float part is float32 with IEEE square
+ *   root and division, evaluated as den = sqrt(vL) * sqrt(vR),
+ *   phi = num / den, 255 * (1 - max(0, phi)); results are reproducible bit
+ *   for bit.
+ *   left, right  uint8 [height][pitch_bytes] device images
+ *   win          5 or 9
+ *   cost_out     uint8 [height][width][ndisp], 16-byte aligned
+ * Errors: SGM_ERR_ARG, SGM_ERR_UNSUPPORTED (win), SGM_ERR_ALIGN.
+ */
+int32_t sgm_cost_ncc(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
+                     int32_t pitch_bytes, int32_t win, int32_t ndisp, uint8_t* cost_out,
+                     void* stream);
+
+/*
  * SGM aggregation, Eq. (sgm_path) and Eq. (sgm_path_aggr) (Sec. 2.1.2):
  *   L_r(p, d) = C(p, d) + min(L'(d), L'(d-1) + P1, L'(d+1) + P1, m' + P2) - m'
  *   with L' = L_r(p - r, .) and m' = min_d L'(d); L_r = C at the first pixel

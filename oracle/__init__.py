@@ -34,8 +34,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-             SRC_PATH, "-o", tmp])
+            ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-ffp-contract=off", "-shared",
+             "-fPIC", SRC_PATH, "-o", tmp, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -64,6 +64,8 @@ def _load():
         lib.sgm_oracle_median9.restype = ctypes.c_uint16
         lib.sgm_oracle_map_reduce_argmin.argtypes = [P, I]
         lib.sgm_oracle_map_reduce_argmin.restype = I
+        lib.sgm_oracle_ncc_cost.argtypes = [P, P, I, I, I, I, P]
+        lib.sgm_oracle_ncc_cost.restype = None
         for name in ("sgm_oracle_census", "sgm_oracle_cost", "sgm_oracle_path",
                      "sgm_oracle_aggregate", "sgm_oracle_aggregate_at",
                      "sgm_oracle_wta", "sgm_oracle_right_disparity",
@@ -100,6 +102,17 @@ def cost(census_left: np.ndarray, census_right: np.ndarray, ndisp: int) -> np.nd
     assert cr.shape == cl.shape and 1 <= ndisp <= 256
     out = np.empty((h, w, ndisp), np.uint8)
     _load().sgm_oracle_cost(_ptr(cl), _ptr(cr), w, h, ndisp, _ptr(out))
+    return out
+
+
+def ncc_cost(left: np.ndarray, right: np.ndarray, win: int, ndisp: int) -> np.ndarray:
+    """Inverted, truncated NCC cost (Sec. 2.1.1, Sec. 2.2.1), round(255 s) as
+    uint8 [H][W][D]; float32 evaluation of the exact integer window sums."""
+    a = _c(left, np.uint8)
+    b = _c(right, np.uint8)
+    h, w = a.shape
+    out = np.empty((h, w, ndisp), np.uint8)
+    _load().sgm_oracle_ncc_cost(_ptr(a), _ptr(b), w, h, win, ndisp, _ptr(out))
     return out
 
 

@@ -19,6 +19,7 @@
  */
 #include "sgm_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -298,4 +299,58 @@ int sgm_oracle_map_reduce_argmin(const uint16_t* values, int n) {
     free(label);
     free(v);
     return best;
+}
+
+/* Inverted, truncated normalised cross-correlation cost (Sec. 2.1.1,
+ * Sec. 2.2.1): s = 1 - max(0, Phi_NCC) over a win x win patch, scaled to the
+ * uint8 cost range as round(255 s).  Readings: pixels outside the image read
+ * as zero (the same zero margin as the census window); a patch with zero
+ * variance has no correlation (Phi = 0, cost 255); x - d < 0 costs 255.
+ * Phi is formed from exact integer window sums,
+ *   Phi = (n S_LR - S_L S_R) / (sqrt(n S_LL - S_L^2) * sqrt(n S_RR - S_R^2)),
+ * then evaluated in float32 in exactly this order with IEEE operations:
+ *   den = sqrtf(vL) * sqrtf(vR); phi = num / den; s = 1 - max(0, phi);
+ *   cost = rint(255 * s) clamped to [0, 255] (ties to even). */
+static int pixel_at(const uint8_t* img, int width, int height, int x, int y) {
+    return inside(x, y, width, height) ? img[(size_t)y * width + x] : 0;
+}
+
+void sgm_oracle_ncc_cost(const uint8_t* left, const uint8_t* right, int width, int height,
+                         int win, int ndisp, uint8_t* cost) {
+    const int r = (win - 1) / 2;
+    const int n = win * win;
+    for (int y = 0; y < height; ++y) {
+        for (int x = 0; x < width; ++x) {
+            for (int d = 0; d < ndisp; ++d) {
+                uint8_t c = 255;
+                if (x - d >= 0) {
+                    long sl = 0, sr = 0, sll = 0, srr = 0, slr = 0;
+                    for (int dy = -r; dy <= r; ++dy) {
+                        for (int dx = -r; dx <= r; ++dx) {
+                            const long a = pixel_at(left, width, height, x + dx, y + dy);
+                            const long b = pixel_at(right, width, height, x - d + dx, y + dy);
+                            sl += a;
+                            sr += b;
+                            sll += a * a;
+                            srr += b * b;
+                            slr += a * b;
+                        }
+                    }
+                    const long num = n * slr - sl * sr;
+                    const long vl = n * sll - sl * sl;
+                    const long vr = n * srr - sr * sr;
+                    if (vl > 0 && vr > 0) {
+                        const float den = sqrtf((float)vl) * sqrtf((float)vr);
+                        const float phi = (float)num / den;
+                        const float s = 1.0f - (phi > 0.0f ? phi : 0.0f);
+                        float v = rintf(255.0f * s);
+                        if (v < 0.0f) v = 0.0f;
+                        if (v > 255.0f) v = 255.0f;
+                        c = (uint8_t)v;
+                    }
+                }
+                cost[((size_t)y * width + x) * ndisp + d] = c;
+            }
+        }
+    }
 }

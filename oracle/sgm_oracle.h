@@ -75,4 +75,8 @@ int sgm_oracle_map_reduce_argmin(const uint16_t* values, int n);
 #ifdef __cplusplus
 }
 #endif
+/* Inverted, truncated NCC cost over win x win patches (win 5 or 9). */
+void sgm_oracle_ncc_cost(const uint8_t* left, const uint8_t* right, int width, int height,
+                         int win, int ndisp, uint8_t* cost);
+
 #endif

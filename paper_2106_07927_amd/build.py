@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsgm.so")
 
-HIP_SOURCES = ["census.hip", "cost.hip", "aggregate.hip", "wta_lrc.hip"]
+HIP_SOURCES = ["census.hip", "cost.hip", "ncc.hip", "aggregate.hip", "wta_lrc.hip"]
 CPP_SOURCES = ["sgm_capi.cpp", "batch.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -114,7 +114,8 @@ const char* sgm_status_string(int32_t status) {
     switch (status) {
         case SGM_OK: return "SGM_OK";
         case SGM_ERR_ARG: return "SGM_ERR_ARG: invalid argument";
-        case SGM_ERR_UNSUPPORTED: return "SGM_ERR_UNSUPPORTED: census window must be 5x5 or 9x7";
+        case SGM_ERR_UNSUPPORTED:
+            return "SGM_ERR_UNSUPPORTED: window must be 5x5 or 9x7 (census) or 5 or 9 (NCC)";
         case SGM_ERR_ALIGN: return "SGM_ERR_ALIGN: misaligned buffer";
         case SGM_ERR_HIP: return "SGM_ERR_HIP: HIP launch failed";
         case SGM_ERR_WORKSPACE: return "SGM_ERR_WORKSPACE: workspace missing or too small";
@@ -154,6 +155,18 @@ int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right, int3
     f.census_right = const_cast<uint64_t*>(census_right);
     f.cost = cost_out;
     return hip_status(sgm::launch_cost(f, as_stream(stream)));
+}
+
+int32_t sgm_cost_ncc(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
+                     int32_t pitch_bytes, int32_t win, int32_t ndisp, uint8_t* cost_out,
+                     void* stream) {
+    if (!left || !right || !cost_out || bad_size(width, height) || pitch_bytes < width)
+        return SGM_ERR_ARG;
+    if (bad_volume(width, height, ndisp)) return SGM_ERR_ARG;
+    if (win != 5 && win != 9) return SGM_ERR_UNSUPPORTED;
+    if (!aligned(cost_out, 16)) return SGM_ERR_ALIGN;
+    return hip_status(sgm::launch_ncc_cost(left, right, width, height, pitch_bytes, win, ndisp,
+                                           cost_out, as_stream(stream)));
 }
 
 size_t sgm_aggregate_work_bytes(int32_t width, int32_t height, int32_t ndisp, int32_t npaths,

@@ -29,8 +29,8 @@ SGM_ERR_ALIGN = -3
 SGM_ERR_HIP = -4
 SGM_ERR_WORKSPACE = -5
 
-EXPORTS = ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_aggregate_work_bytes", "sgm_wta_lrc",
-           "sgm_wta_lrc_work_elems", "sgm_aggregate_select", "sgm_aggregate_select_work_bytes",
+EXPORTS = ("sgm_census", "sgm_cost", "sgm_cost_ncc", "sgm_aggregate", "sgm_aggregate_work_bytes",
+           "sgm_wta_lrc", "sgm_wta_lrc_work_elems", "sgm_aggregate_select", "sgm_aggregate_select_work_bytes",
            "sgm_aggregate_select_subpixel", "sgm_aggregate_select_subpixel_work_bytes",
            "sgm_disparity_exact_lr", "sgm_disparity_exact_lr_work_bytes",
            "sgm_batch_workspace_bytes", "sgm_batch_plan_create",
@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     P, I32 = ctypes.c_void_p, ctypes.c_int32
     lib.sgm_census.argtypes = [P, I32, I32, I32, I32, I32, P, P]
     lib.sgm_cost.argtypes = [P, P, I32, I32, I32, P, P]
+    lib.sgm_cost_ncc.argtypes = [P, P, I32, I32, I32, I32, I32, P, P]
+    lib.sgm_cost_ncc.restype = I32
     lib.sgm_aggregate.argtypes = [P, I32, I32, I32, I32, I32, I32, P, P, ctypes.c_size_t, P]
     lib.sgm_aggregate_work_bytes.argtypes = [I32, I32, I32, I32, I32]
     lib.sgm_aggregate_work_bytes.restype = ctypes.c_size_t
@@ -185,6 +187,21 @@ def sgm_cost(census_left: torch.Tensor, census_right: torch.Tensor, ndisp: int,
     _expect(out, torch.uint8, (h, w, ndisp), "out")
     _check(load_library().sgm_cost(_ptr(census_left), _ptr(census_right), w, h, ndisp,
                                    _ptr(out), _stream(stream)))
+    return out
+
+
+def sgm_cost_ncc(left: torch.Tensor, right: torch.Tensor, win: int, ndisp: int,
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Inverted, truncated NCC cost volume (win 5 or 9); uint8 [H][W][ndisp]."""
+    if left.dtype != torch.uint8 or left.dim() != 2 or right.shape != left.shape or \
+            right.dtype != torch.uint8:
+        raise ValueError("left and right must be uint8 [H][W] tensors of one shape")
+    h, w = left.shape
+    if out is None:
+        out = _empty((h, w, ndisp), torch.uint8, left.device)
+    _expect(out, torch.uint8, (h, w, ndisp), "out")
+    _check(load_library().sgm_cost_ncc(_ptr(left), _ptr(right), w, h, w, win, ndisp, _ptr(out),
+                                       _stream(stream)))
     return out
 
 

@@ -73,6 +73,15 @@ def test_cost_validation(lib):
     assert f(P(FAKE + 4), P(FAKE), 8, 8, 16, P(FAKE), P(NULL)) == ALIGN
 
 
+def test_cost_ncc_validation(lib):
+    f = lib.sgm_cost_ncc
+    assert f(P(NULL), P(FAKE), 8, 8, 8, 5, 16, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 8, 8, 7, 5, 16, P(FAKE), P(NULL)) == ARG      # pitch < width
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 5, 0, P(FAKE), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 7, 16, P(FAKE), P(NULL)) == UNSUP
+    assert f(P(FAKE), P(FAKE), 8, 8, 8, 9, 16, P(FAKE + 8), P(NULL)) == ALIGN
+
+
 def test_aggregate_validation(lib):
     f = lib.sgm_aggregate
     big = 1 << 40
