@@ -378,8 +378,13 @@ __global__ __launch_bounds__(kThreads) void paths_kernel(Frame f) {
 template <int NH, int LH, int NO, int LO, bool ALH, bool PDH, bool ALO, bool PDO, bool U8>
 __global__ __launch_bounds__(kThreads) void paths_batch_kernel(WorkList wl) {
     for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
-        const int fi = find_frame(wl, b);
-        paths_block<NH, LH, NO, LO, ALH, PDH, ALO, PDO, U8>(wl.frames[fi], b - wl.starts[fi]);
+        if (wl.items) {
+            paths_block<NH, LH, NO, LO, ALH, PDH, ALO, PDO, U8>(wl.frames[wl.items[2 * b]],
+                                                               wl.items[2 * b + 1]);
+        } else {
+            const int fi = find_frame(wl, b);
+            paths_block<NH, LH, NO, LO, ALH, PDH, ALO, PDO, U8>(wl.frames[fi], b - wl.starts[fi]);
+        }
     }
 }
 
@@ -475,7 +480,9 @@ hipError_t launch_paths_layout(const Frame* one, const WorkList* wl, int ndisp, 
     const bool alo = ndisp % (2 * NO) == 0;
     const bool pdh = LH * 2 * NH > ndisp;
     const bool pdo = LO * 2 * NO > ndisp;
-    const int grid = one ? nblocks : persistent_grid(nblocks);
+    // an ordered item list is dispatched one block per item, so the hardware
+    // hands out the longest lines first
+    const int grid = (one || wl->items) ? nblocks : persistent_grid(nblocks);
 #define SGM_PATHS(A, B, C, D, U)                                                                   \
     do {                                                                                           \
         if (one) paths_kernel<NH, LH, NO, LO, A, B, C, D, U><<<grid, kThreads, 0, stream>>>(*one); \
@@ -555,6 +562,11 @@ int default_variant(int width, int height, int ndisp) {
     if (px >= 1500000) return 1;
     if (ndisp > 64 && px >= 400000) return 2;
     return 0;
+}
+
+int path_horizontal_blocks(int width, int height, int ndisp, int variant) {
+    const PathLayout l = path_layout(ndisp, variant);
+    return dir_blocks(0, width, height, l.lpl_h, l.lpl_o) + dir_blocks(1, width, height, l.lpl_h, l.lpl_o);
 }
 
 int path_blocks(int width, int height, int ndisp, int npaths, int variant) {

@@ -18,6 +18,7 @@
 // Running the plan is one hipGraphLaunch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -93,6 +94,7 @@ struct Launch {
     int ndisp, variant;
     std::vector<int> frames;
     size_t frames_off = 0, starts_off = 0;   // workspace offsets of its tables
+    size_t items_off = 0;                    // path stage: ordered (frame, block) list
     WorkList wl{};
 };
 
@@ -191,6 +193,12 @@ size_t build_layout(const sgm_pair* pairs, int32_t n, const sgm_params* p, const
         off += align256(L.frames.size() * sizeof(Frame));
         L.starts_off = off;
         off += align256((L.frames.size() + 1) * sizeof(int32_t));
+        if (L.stage == kPaths) {
+            size_t items = 0;
+            for (int k : L.frames) items += stage_blocks(kPaths, (*frames)[k]);
+            L.items_off = off;
+            off += align256(2 * items * sizeof(int32_t));
+        }
     }
     return off;
 }
@@ -254,6 +262,28 @@ int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n, const sgm_params
         L.wl.starts = reinterpret_cast<const int32_t*>(base + L.starts_off);
         L.wl.nframes = (int32_t)L.frames.size();
         L.wl.total = acc;
+        L.wl.items = nullptr;
+        if (L.stage == kPaths) {
+            // every block of the group, longest lines first: a block walks
+            // W steps on the horizontal paths and H steps on the others
+            struct Item { int32_t steps, frame, block; };
+            std::vector<Item> items;
+            for (size_t k = 0; k < L.frames.size(); ++k) {
+                const Frame& f = ft[k];
+                const int nh = path_horizontal_blocks(f.width, f.height, f.ndisp, f.variant);
+                const int nb = stage_blocks(kPaths, f);
+                for (int b = 0; b < nb; ++b)
+                    items.push_back({b < nh ? f.width : f.height, (int32_t)k, b});
+            }
+            std::stable_sort(items.begin(), items.end(),
+                             [](const Item& a, const Item& b) { return a.steps > b.steps; });
+            int32_t* it = reinterpret_cast<int32_t*>(host.data() + (L.items_off - tables_off));
+            for (size_t i = 0; i < items.size(); ++i) {
+                it[2 * i] = items[i].frame;
+                it[2 * i + 1] = items[i].block;
+            }
+            L.wl.items = reinterpret_cast<const int32_t*>(base + L.items_off);
+        }
     }
     hipError_t e = hipMemcpy(base + tables_off, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {

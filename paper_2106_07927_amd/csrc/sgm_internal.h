@@ -162,6 +162,10 @@ struct WorkList {
     const int32_t* starts;           // nframes + 1 entries
     int32_t nframes;
     int32_t total;                   // starts[nframes]
+    // optional: total (frame, block) pairs giving the launch order of the
+    // blocks (longest first); when set, block b of the launch is items[2b],
+    // items[2b + 1] instead of the frame-major order of starts
+    const int32_t* items;
 };
 
 __device__ __forceinline__ int find_frame(const WorkList& wl, int b) {
@@ -177,7 +181,12 @@ __device__ __forceinline__ int find_frame(const WorkList& wl, int b) {
 // Grid of a persistent launch: enough blocks to fill the GPU, never more than
 // there is work.
 inline int persistent_grid(int total_blocks, int per_cu = 8) {
+#ifdef SGM_FULL_GRID
+    (void)per_cu;
+    return std::max(1, total_blocks);
+#else
     return std::max(1, std::min(total_blocks, 256 * per_cu));
+#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -227,6 +236,8 @@ int path_variants(int ndisp);                       // number of variants (>= 1)
 int default_variant(int width, int height, int ndisp);
 PathLayout path_layout(int ndisp, int variant);
 int path_blocks(int width, int height, int ndisp, int npaths, int variant);
+// blocks of the horizontal directions, which come first in a frame's block order
+int path_horizontal_blocks(int width, int height, int ndisp, int variant);
 size_t aggregate_slice_elems(int width, int height, int ndisp);
 size_t aggregate_work_bytes(int width, int height, int ndisp, int npaths, int p2);
 
