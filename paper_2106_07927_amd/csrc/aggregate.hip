@@ -350,6 +350,16 @@ __device__ __forceinline__ void paths_block(const Frame& f, int lb) {
     // keep two chunks of cost bytes in registers
     constexpr int KH = NH == 1 ? kStepsH1 : kStepsH2;
     constexpr int KO = NO <= 4 ? kStepsO4 : kStepsO8;
+    if (f.paths_fill_keys) {
+        // the D^R key map of the selection that follows starts at "no
+        // candidate"; every block clears an equal share of it
+        int nb = 0;
+        for (int i = 0; i < f.npaths; ++i) nb += dir_blocks(i, f.width, f.height, LH, LO);
+        const size_t n = (size_t)f.width * f.height;
+        const size_t per = (n + nb - 1) / nb;
+        const size_t e1 = min(n, (size_t)(lb + 1) * per);
+        for (size_t e = (size_t)lb * per + threadIdx.x; e < e1; e += blockDim.x) f.right_keys[e] = 0xFFFFFFFFu;
+    }
     int block0, di;
     const DirTask task = find_dir(lb, f.width, f.height, f.npaths, LH, LO, &block0, &di);
     const int wave_in_dir = (lb - block0) * kWaves + (int)(threadIdx.x >> 6);

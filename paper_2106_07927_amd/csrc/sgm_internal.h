@@ -139,6 +139,7 @@ struct Frame {
     int32_t width, height, ndisp, pitch;
     int32_t win_w, win_h, npaths, p1, p2, lr_tolerance, median3x3;
     int32_t variant;                 // lane-layout variant of the path kernel (< 0: default)
+    int32_t paths_fill_keys;         // the path kernel also sets right_keys to all ones
     const uint8_t* left;
     const uint8_t* right;
     uint64_t* census_left;

@@ -657,11 +657,9 @@ bool fused_select_supported(int ndisp, int npaths, int p2) {
 }
 
 hipError_t launch_aggregate_select(const Frame& f, hipStream_t stream, bool fine) {
-    hipError_t e = launch_paths(f, stream);
-    if (e != hipSuccess) return e;
-    const size_t n = (size_t)f.width * f.height;
-    fill_keys_kernel<<<fill_blocks(n), 256, 0, stream>>>(f);
-    e = hipGetLastError();
+    Frame g = f;
+    g.paths_fill_keys = 1;                     // the path kernel clears the D^R keys
+    hipError_t e = launch_paths(g, stream);
     if (e != hipSuccess) return e;
     if (fine) launch_fused_any<true>(&f, nullptr, f.ndisp, f.npaths, f.p2, stream);
     else launch_fused_any<false>(&f, nullptr, f.ndisp, f.npaths, f.p2, stream);

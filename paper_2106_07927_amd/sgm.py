@@ -384,6 +384,22 @@ class StereoSGM:
                         out_right=self.disp_right, work=self.work, stream=stream)
         return self.disp
 
+    def capture(self, left: torch.Tensor, right: torch.Tensor):
+        """Captures run(left, right) into a HIP graph (torch.cuda.CUDAGraph)
+        and returns it: graph.replay() re-runs the path on whatever the two
+        input tensors hold, into this object's buffers.  The library's calls
+        allocate nothing and never synchronise, so they capture as they
+        are."""
+        side = torch.cuda.Stream(device=left.device)
+        side.wait_stream(torch.cuda.current_stream(left.device))
+        with torch.cuda.stream(side):
+            self.run(left, right)                  # warm-up outside the graph
+        torch.cuda.current_stream(left.device).wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.run(left, right)
+        return graph
+
 
 def _params_struct(p: Params) -> SgmParams:
     return SgmParams(p.win_w, p.win_h, p.npaths, p.p1, p.p2, p.lr_tolerance, int(bool(p.median3x3)))

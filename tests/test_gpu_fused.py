@@ -3,11 +3,10 @@ with WTA, approximate D^R, LR check and median; S_bar never leaves the chip)
 against the CPU oracle, and against the four-call path on the same inputs.
 Integer throughout, so every comparison is exact.
 
-Shapes cover: widths below, at and above the 128-pixel row segment of the
-selection pass and ragged last chunks; every disparity range class of the
-fused kernel (D % 16 == 0 with 1, 2 and 4 disparities per lane) and the
-unfused fallbacks (D % 16 != 0, P2 > 255); P2 = 127 / 128 on either side of
-the bytewise pair-sum limit; 4 and 8 paths.
+Shapes cover: widths below, at and above the 64-pixel tile of the fused
+pass and ragged last tiles; disparity ranges from 16 to 256 (D % 16 == 0)
+and the unfused fallbacks (D % 16 != 0, P2 > 255); P2 = 127 / 128 on either
+side of the bytewise pair-sum limit; 4 and 8 paths; graph replays.
 """
 import sys
 
@@ -146,3 +145,36 @@ def test_fused_equals_four_calls_large(dev):
     four.run(l, r)
     np.testing.assert_array_equal(d_f, host(four.disp))
     np.testing.assert_array_equal(dr_f, host(four.disp_right))
+
+
+def test_graph_replays_match_eager(dev):
+    """The path captured into a HIP graph: every replay, with eager work and
+    new inputs between replays, equals the eager result for those inputs."""
+    import torch
+    from paper_2106_07927_amd import sgm
+    say("graph replays")
+    w, h, nd = 300, 64, 128
+    prm = sgm.Params(win_w=9, win_h=7, ndisp=nd, npaths=8, p1=10, p2=120, lr_tolerance=1,
+                     median3x3=True)
+    eng = sgm.StereoSGM(w, h, prm, device=dev)
+    ref_eng = sgm.StereoSGM(w, h, prm, device=dev)
+    l = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    r = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    pairs = [datagen.make_pair(w, h, nd, seed=900 + i, planes=(3, 5)) for i in range(4)]
+    l.copy_(torch.from_numpy(pairs[0]["left"]))
+    r.copy_(torch.from_numpy(pairs[0]["right"]))
+    graph = eng.capture(l, r)
+    for i, p in enumerate(pairs + pairs[:1]):
+        l.copy_(torch.from_numpy(p["left"]))
+        r.copy_(torch.from_numpy(p["right"]))
+        graph.replay()
+        torch.cuda.synchronize()
+        got_d, got_r = eng.disp.clone(), eng.disp_right.clone()
+        ref_eng.run(l, r)                          # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(got_d, ref_eng.disp), i
+        assert torch.equal(got_r, ref_eng.disp_right), i
+    ref = oracle.run(pairs[0]["left"], pairs[0]["right"],
+                     oracle.Params(win_w=9, win_h=7, ndisp=nd, npaths=8, p1=10, p2=120,
+                                   lr_tolerance=1, median3x3=True))
+    np.testing.assert_array_equal(eng.disp.cpu().numpy(), ref["disp"])
