@@ -44,7 +44,7 @@ def parse():
                     help="timed replays of the 64-pair batch (0 skips the batched form)")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the served trace (0 skips the served form)")
-    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the path, run a plain device copy of this many MiB five "
                          "times (the known-size kernel that scales HBM counter readings)")
@@ -404,8 +404,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic("sgm_aggregate_select", digest),
-                     "kernel": "sgm_aggregate_select (paths_kernel + fill_u32_kernel + "
-                               "select_fused_kernel + check_median_kernel)",
+                     "kernel": "sgm_aggregate_select (paths_kernel + select_fused_kernel + "
+                               "check_median_kernel)",
                      "algorithmic_bytes": sel_bytes},
         "four_call": {"ms_per_step": round(four["ms_per_step"], 5),
                       "value": round(des / (four["ms_per_step"] * 1e-3) / 1e6, 1),

@@ -41,27 +41,17 @@ namespace {
 
 constexpr uint32_t kBig = 0x7FFFu;
 constexpr uint32_t kBig2 = 0x7FFF7FFFu;
-constexpr int kWaves = 4;
+constexpr int kWaves = 4;                 // waves per block of the path kernel
 constexpr int kThreads = 64 * kWaves;
 
 enum Kind : int { kHorizontal = 0, kVertical = 1, kDiagonal = 2 };
 
 // Steps per chunk of the path loop, by lane layout (horizontal lines with one
 // / more packed registers per lane, other lines with <= 4 / 8 registers).
-#ifndef SGM_STEPS_H1
-#define SGM_STEPS_H1 32
-#endif
-#ifndef SGM_STEPS_H2
-#define SGM_STEPS_H2 16
-#endif
-#ifndef SGM_STEPS_O4
-#define SGM_STEPS_O4 16
-#endif
-#ifndef SGM_STEPS_O8
-#define SGM_STEPS_O8 8
-#endif
-constexpr int kStepsH1 = SGM_STEPS_H1, kStepsH2 = SGM_STEPS_H2;
-constexpr int kStepsO4 = SGM_STEPS_O4, kStepsO8 = SGM_STEPS_O8;
+// Chunks of 8 to 48 steps time the same on the 1242x375, D = 128 frame: the
+// kernel is bound by HBM traffic, so these only bound the register use.
+constexpr int kStepsH1 = 32, kStepsH2 = 16;
+constexpr int kStepsO4 = 16, kStepsO8 = 8;
 
 struct DirTask {
     int dx, dy;      // step r: the predecessor of p is p - r

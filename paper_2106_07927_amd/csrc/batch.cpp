@@ -82,7 +82,7 @@ int stage_blocks(Stage st, const Frame& f) {
         case kMerge: return merge_blocks(n * f.ndisp);
         case kFill: return fill_blocks(n);
         case kSelect: return select_blocks_x(f.width) * f.height;
-        case kFused: return fused_blocks_x(f.width) * f.height;
+        case kFused: return fused_blocks_x(f.width, f.ndisp) * f.height;
         case kMedian: return median_blocks(f.width, f.height);
         default: return 0;
     }

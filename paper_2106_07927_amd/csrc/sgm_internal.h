@@ -182,12 +182,7 @@ __device__ __forceinline__ int find_frame(const WorkList& wl, int b) {
 // Grid of a persistent launch: enough blocks to fill the GPU, never more than
 // there is work.
 inline int persistent_grid(int total_blocks, int per_cu = 8) {
-#ifdef SGM_FULL_GRID
-    (void)per_cu;
-    return std::max(1, total_blocks);
-#else
     return std::max(1, std::min(total_blocks, 256 * per_cu));
-#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -211,9 +206,15 @@ __host__ __device__ inline int select_blocks_x(int w) {
 }
 
 // pixels of one row per block of the fused path-sum + selection pass
+// (at most 8192 volume elements per tile, so every thread sums two 16-byte
+// blocks: 64 pixels up to D = 128, 32 beyond)
 constexpr int kFusedTile = 64;
 constexpr int kMaxFusedD = 256;
-__host__ __device__ inline int fused_blocks_x(int w) { return (w + kFusedTile - 1) / kFusedTile; }
+__host__ __device__ inline int fused_tile_px(int ndisp) { return ndisp > 128 ? 32 : kFusedTile; }
+__host__ __device__ inline int fused_blocks_x(int w, int ndisp) {
+    const int t = fused_tile_px(ndisp);
+    return (w + t - 1) / t;
+}
 
 constexpr int kMedianTileW = 64;
 constexpr int kMedianTileH = 4;

@@ -261,14 +261,16 @@ __device__ __forceinline__ void select_block(SelectTile<FINE>& st, const uint16_
 }
 
 // ---- path sum fused with the selection pass --------------------------------
-// A block owns a tile of kFusedTile pixels of one row.
-//  (1) Its threads sum the tile's 16-byte blocks of the cost volume and of the
-//      uint8 penalty slices (merge16) into an LDS copy of S_bar: one row of D
-//      values per pixel, padded by one dword so that rows start in different
-//      banks.  S_bar never goes to HBM.
-//  (2) Four threads per pixel take the minimum key (S_bar << 8) | d over a
-//      quarter of the disparities each; a quad reduction gives D^L (and with
-//      FINE the refined value, from the winner's two neighbours in LDS).
+// A block owns a tile of one row: 64 pixels, or 32 when D > 128, so that the
+// tile holds at most 8192 volume elements.
+//  (1) Each of its 256 threads loads two 16-byte blocks of the tile from the
+//      cost volume and from every uint8 penalty slice -- all loads issued
+//      before any is used -- and sums them (merge16) into an LDS copy of
+//      S_bar: one row of D values per pixel, padded by one dword so that rows
+//      start in different banks.  S_bar never goes to HBM.
+//  (2) 256 / tile threads per pixel take the minimum key (S_bar << 8) | d
+//      over their share of the disparities; a DPP reduction gives D^L (and
+//      with FINE the refined value, from the winner's two neighbours in LDS).
 //  (3) One thread per right-view pixel q folds key(q + d, d) over the d with
 //      q + d inside the tile and merges that partial minimum into the D^R key
 //      map with atomicMin; the tiles holding q .. q + D - 1 complete it.
@@ -277,37 +279,48 @@ template <int NP, bool PAIR, bool FINE>
 __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, const Frame& f, int bx,
                                                   int y) {
     const int width = f.width, ndisp = f.ndisp;
-    const int x0 = bx * kFusedTile;
-    const int npx = min(kFusedTile, width - x0);
+    const int tpx = fused_tile_px(ndisp);
+    const int x0 = bx * tpx;
+    const int npx = min(tpx, width - x0);
     const int rs = ndisp + 2;                      // LDS row stride (uint16)
     const size_t row = (size_t)y * width;
     const uint32_t e_tile = (uint32_t)(row + x0) * (uint32_t)ndisp;
     const uint32_t e_last = (uint32_t)(row + x0 + npx) * (uint32_t)ndisp - 16u;
 
-    // (1) path sum into LDS; blocks past the row's last pixel re-read its
-    // last block and land in LDS rows that are never read
-    const int nblk = kFusedTile * ndisp / 16;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        const uint32_t e = min(e_tile + 16u * (uint32_t)b, e_last);
-        const uint4 c = *reinterpret_cast<const uint4*>(f.cost + e);
-        uint4 a[NP];
+    // (1) path sum into LDS.  Blocks past the row's last pixel re-read its
+    // last block and land in LDS rows that are never read.
+    const int nblk = tpx * ndisp / 16;             // <= 512
+    uint4 c[2];
+    uint4 a[2][NP];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (256 * i >= nblk) break;                // uniform: small D fits in one pass
+        const uint32_t e = min(e_tile + 16u * (uint32_t)(threadIdx.x + 256 * i), e_last);
+        c[i] = *reinterpret_cast<const uint4*>(f.cost + e);
 #pragma unroll
         for (int r = 0; r < NP; ++r)
-            a[r] = *reinterpret_cast<const uint4*>(f.slices + (size_t)r * f.slice_stride + e);
-        uint32_t sum[8];
-        merge16<NP, PAIR>(c, a, sum);
-        const int p = (16 * b) / ndisp;
-        const int d = 16 * b - p * ndisp;
-        uint32_t* dst = reinterpret_cast<uint32_t*>(sb + p * rs + d);
+            a[i][r] = *reinterpret_cast<const uint4*>(f.slices + (size_t)r * f.slice_stride + e);
+    }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) dst[k] = sum[k];
+    for (int i = 0; i < 2; ++i) {
+        const int b = threadIdx.x + 256 * i;
+        if (b < nblk) {
+            uint32_t sum[8];
+            merge16<NP, PAIR>(c[i], a[i], sum);
+            const int p = (16 * b) / ndisp;
+            const int d = 16 * b - p * ndisp;
+            uint32_t* dst = reinterpret_cast<uint32_t*>(sb + p * rs + d);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dst[k] = sum[k];
+        }
     }
     __syncthreads();
 
-    // (2) D^L: quad (p, part) covers disparities part * D/4 .. (part+1) * D/4 - 1
+    // (2) D^L: the tpp threads of pixel p each cover D / tpp disparities
     {
-        const int p = threadIdx.x >> 2, part = threadIdx.x & 3;
-        const int dq = ndisp >> 2;
+        const int tpp = 256 / tpx;                 // 4 or 8
+        const int p = threadIdx.x / tpp, part = threadIdx.x % tpp;
+        const int dq = ndisp / tpp;
         uint32_t best = kInf;
         if (p < npx) {
             const uint16_t* src = sb + p * rs + part * dq;
@@ -319,6 +332,7 @@ __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, con
         }
         best = min(best, dpp<kDppQuadSwap1>(kInf, best));
         best = min(best, dpp<kDppQuadSwap2>(kInf, best));
+        if (tpp == 8) best = min(best, dpp<kDppRowHalfMirror>(kInf, best));
         if (part == 0 && p < npx) {
             const int d = (int)(best & 0xFFu);
             f.disp_left[row + x0 + p] = (uint16_t)d;
@@ -346,9 +360,9 @@ __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, con
     __syncthreads();   // the LDS tile is reused by the next work item
 }
 
-// LDS of the fused pass: kFusedTile rows of D + 2 values, sized at launch
+// LDS of the fused pass: one row of D + 2 values per tile pixel, sized at launch
 __host__ __device__ inline size_t fused_lds_bytes(int ndisp) {
-    return (size_t)kFusedTile * (size_t)(ndisp + 2) * sizeof(uint16_t);
+    return (size_t)fused_tile_px(ndisp) * (size_t)(ndisp + 2) * sizeof(uint16_t);
 }
 
 template <int NP, bool PAIR, bool FINE>
@@ -364,7 +378,7 @@ __global__ __launch_bounds__(256) void select_fused_batch_kernel(WorkList wl) {
         const int fi = find_frame(wl, b);
         const Frame& f = wl.frames[fi];
         const int lb = b - wl.starts[fi];
-        const int bxs = fused_blocks_x(f.width);
+        const int bxs = fused_blocks_x(f.width, f.ndisp);
         select_tile_block<NP, PAIR, false>(sb, f, lb % bxs, lb / bxs);
     }
 }
@@ -559,7 +573,7 @@ template <int NP, bool PAIR, bool FINE>
 void launch_fused_t(const Frame* one, const WorkList* wl, int ndisp, hipStream_t stream) {
     const size_t lds = fused_lds_bytes(ndisp);
     if (one) {
-        const dim3 g(fused_blocks_x(one->width), one->height);
+        const dim3 g(fused_blocks_x(one->width, ndisp), one->height);
         select_fused_kernel<NP, PAIR, FINE><<<g, 256, lds, stream>>>(*one);
     } else {
         select_fused_batch_kernel<NP, PAIR><<<persistent_grid(wl->total), 256, lds, stream>>>(*wl);
