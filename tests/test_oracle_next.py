@@ -32,6 +32,12 @@ def test_exact_right_disparity_equals_right_reference_definition(oracle_lib, win
             c_r[:, : w - d, d] = np.bitwise_count(cr[:, : w - d] ^ cl[:, d:]).astype(np.uint8)
     direct = oracle.wta(oracle.aggregate(c_r, npaths, prm.p1, prm.p2))
     np.testing.assert_array_equal(oracle.exact_right_disparity(left, right, prm), direct)
+    # the whole exact-check path carries that map, not the approximation of
+    # Eq. (right_disparity), which differs on these images
+    out = oracle.run_exact_lr(left, right, prm)
+    np.testing.assert_array_equal(out["disp_right"], direct)
+    approx = oracle.run(left, right, prm)["disp_right"]
+    assert np.any(approx != direct)
 
 
 @pytest.mark.parametrize("d0", [0, 3, 11])
