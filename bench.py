@@ -188,8 +188,8 @@ def other_forms(args, torch, sgm, eng, left, right, prm, stream, des):
                                     left.device)
 
     def fine():
-        sgm.sgm_census(left, prm.win_w, prm.win_h, out=eng.census_left)
-        sgm.sgm_census(right, prm.win_w, prm.win_h, out=eng.census_right)
+        sgm.sgm_census_pair(left, right, prm.win_w, prm.win_h, out_left=eng.census_left,
+                            out_right=eng.census_right)
         sgm.sgm_cost(eng.census_left, eng.census_right, prm.ndisp, out=eng.cost)
         sgm.sgm_aggregate_select_subpixel(eng.cost, prm.npaths, prm.p1, prm.p2, prm.lr_tolerance,
                                           prm.median3x3, out=fine_out, work=fine_work)
@@ -284,8 +284,12 @@ def main():
                 if ev is not None:
                     ev[i].record(stream)
             mark(0)
-            sgm.sgm_census(left, prm.win_w, prm.win_h, out=eng.census_left)
-            sgm.sgm_census(right, prm.win_w, prm.win_h, out=eng.census_right)
+            if fused:
+                sgm.sgm_census_pair(left, right, prm.win_w, prm.win_h, out_left=eng.census_left,
+                                    out_right=eng.census_right)
+            else:
+                sgm.sgm_census(left, prm.win_w, prm.win_h, out=eng.census_left)
+                sgm.sgm_census(right, prm.win_w, prm.win_h, out=eng.census_right)
             mark(1)
             sgm.sgm_cost(eng.census_left, eng.census_right, nd, out=eng.cost)
             mark(2)

@@ -69,6 +69,19 @@ int32_t sgm_census(const uint8_t* img, int32_t width, int32_t height,
                    uint64_t* census_out, void* stream);
 
 /*
+ * Census transform of both images of a pair in one launch (Sec. 2.2.1): the
+ * same descriptors as sgm_census on left and on right, with one launch
+ * latency instead of two.  Both images share width, height and pitch.
+ *   left, right                       uint8 [height][pitch_bytes]
+ *   census_left_out, census_right_out uint64 [height][width], 8-byte aligned,
+ *                                     distinct buffers
+ * Errors: as sgm_census; SGM_ERR_ARG also when the two outputs coincide.
+ */
+int32_t sgm_census_pair(const uint8_t* left, const uint8_t* right, int32_t width,
+                        int32_t height, int32_t pitch_bytes, int32_t win_w, int32_t win_h,
+                        uint64_t* census_left_out, uint64_t* census_right_out, void* stream);
+
+/*
  * Matching-cost volume, Eq. (image_matching) with Phi the Hamming distance of
  * census descriptors (Sec. 2.1.1):
  *   C(x, y, d) = popcount(CL(x, y) ^ CR(x - d, y))   if x - d >= 0

@@ -48,8 +48,8 @@ enum Kind : int { kHorizontal = 0, kVertical = 1, kDiagonal = 2 };
 
 // Steps per chunk of the path loop, by lane layout (horizontal lines with one
 // / more packed registers per lane, other lines with <= 4 / 8 registers).
-// Chunks of 8 to 48 steps time the same on the 1242x375, D = 128 frame: the
-// kernel is bound by HBM traffic, so these only bound the register use.
+// Halving them times the same on the 1242x375, D = 128 frame; 1.5x as many
+// no longer fit the registers of the 8-register layout.
 constexpr int kStepsH1 = 32, kStepsH2 = 16;
 constexpr int kStepsO4 = 16, kStepsO8 = 8;
 
@@ -181,33 +181,60 @@ __device__ __forceinline__ uint32_t cost_pair(const CostVec<NREG>& c, int k) {
     return __builtin_amdgcn_perm(0u, c.w[k >> 1], (k & 1) ? 0x0c030c02u : 0x0c010c00u);
 }
 
-// Writes the step's output of one lane: penalty bytes (U8) or path values.
+// Raw buffer over a uint8 slice: the hardware range check drops a store at
+// a byte offset >= `bytes`, so lanes that must not write (padding
+// disparities, lines past the direction's end) carry kNoWrite added to their
+// offsets and store unconditionally, without an exec-mask branch per step.
+// Valid offsets are < 2^31 (volume limit), so biased ones stay in
+// [2^31, 2^32) and never wrap back into range.
+constexpr uint32_t kNoWrite = 0x80000000u;
+constexpr int kRawBufferWord3 = 0x00020000;     // 32-bit data format, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, kRawBufferWord3);
+}
+
+// Writes the step's output of one lane: penalty bytes through the slice's
+// buffer resource (U8; `off` is the biased byte offset of the lane's first
+// disparity, `eoff` the per-element offsets of the unaligned form), or path
+// values (uint16) through a plain pointer, guarded by `write`.
 template <int NREG, bool ALIGNED, bool U8>
-__device__ __forceinline__ void store_out(void* __restrict__ slice, uint32_t off, int d0, int ndisp,
+__device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, uint16_t* __restrict__ wide,
+                                          uint32_t off, bool write, int d0, int ndisp,
+                                          const uint32_t (&eoff)[2 * NREG],
                                           const uint32_t (&A)[NREG], const uint32_t (&L)[NREG]) {
     if constexpr (U8) {
-        uint8_t* p = static_cast<uint8_t*>(slice) + off;
         if constexpr (ALIGNED) {
             if constexpr (NREG == 1) {
-                *reinterpret_cast<uint16_t*>(p) = (uint16_t)__builtin_amdgcn_perm(0u, A[0], 0x0c0c0200u);
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__builtin_amdgcn_perm(0u, A[0], 0x0c0c0200u),
+                                                      rs, off, 0, 0);
             } else if constexpr (NREG == 2) {
-                *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(A[1], A[0], 0x06040200u);
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_perm(A[1], A[0], 0x06040200u), rs, off,
+                                                      0, 0);
             } else if constexpr (NREG == 4) {
-                *reinterpret_cast<uint2*>(p) = make_uint2(__builtin_amdgcn_perm(A[1], A[0], 0x06040200u),
-                                                          __builtin_amdgcn_perm(A[3], A[2], 0x06040200u));
+                typedef uint32_t v2 __attribute__((ext_vector_type(2)));
+                v2 v;
+                v.x = __builtin_amdgcn_perm(A[1], A[0], 0x06040200u);
+                v.y = __builtin_amdgcn_perm(A[3], A[2], 0x06040200u);
+                __builtin_amdgcn_raw_buffer_store_b64(v, rs, off, 0, 0);
             } else {
-                *reinterpret_cast<uint4*>(p) = make_uint4(__builtin_amdgcn_perm(A[1], A[0], 0x06040200u),
-                                                          __builtin_amdgcn_perm(A[3], A[2], 0x06040200u),
-                                                          __builtin_amdgcn_perm(A[5], A[4], 0x06040200u),
-                                                          __builtin_amdgcn_perm(A[7], A[6], 0x06040200u));
+                typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+                v4 v;
+                v.x = __builtin_amdgcn_perm(A[1], A[0], 0x06040200u);
+                v.y = __builtin_amdgcn_perm(A[3], A[2], 0x06040200u);
+                v.z = __builtin_amdgcn_perm(A[5], A[4], 0x06040200u);
+                v.w = __builtin_amdgcn_perm(A[7], A[6], 0x06040200u);
+                __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 0);
             }
         } else {
 #pragma unroll
             for (int e = 0; e < 2 * NREG; ++e)
-                if (d0 + e < ndisp) p[e] = (uint8_t)((e & 1) ? (A[e >> 1] >> 16) : A[e >> 1]);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)((e & 1) ? (A[e >> 1] >> 16) : A[e >> 1]), rs,
+                                                     off + eoff[e], 0, 0);
         }
     } else {
-        uint16_t* p = static_cast<uint16_t*>(slice) + off;
+        if (!write) return;
+        uint16_t* p = wide + off;
         if constexpr (ALIGNED) {
             uint32_t* q = reinterpret_cast<uint32_t*>(p);
 #pragma unroll
@@ -220,11 +247,14 @@ __device__ __forceinline__ void store_out(void* __restrict__ slice, uint32_t off
     }
 }
 
-// One wave's lines of one direction, the whole way along.
+// One wave's lines of one direction, the whole way along.  Positions are
+// carried as volume offsets that advance by one uniform stride per step;
+// only a diagonal line tracks its column, to wrap at the border.
 template <int KIND, int NREG, int LPL, int K, bool ALIGNED, bool PADDED, bool U8>
 __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void* __restrict__ slice,
-                                          int width, int height, int ndisp, uint32_t p1x2,
-                                          uint32_t p2x2, const DirTask& task, int wave_in_dir) {
+                                          uint32_t slice_bytes, int width, int height, int ndisp,
+                                          uint32_t p1x2, uint32_t p2x2, const DirTask& task,
+                                          int wave_in_dir) {
     constexpr int DPL = 2 * NREG;
     constexpr int LPW = 64 / LPL;
     const int lane = threadIdx.x & 63;
@@ -239,7 +269,8 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
     const bool last_lane = sub == LPL - 1;
     const int dx = task.dx, dy = task.dy;
     const int nsteps = task.nsteps;
-    const uint32_t pix_bytes = (uint32_t)ndisp;
+    const __amdgpu_buffer_rsrc_t rs = slice_rsrc(slice, slice_bytes);
+    uint16_t* const wide = static_cast<uint16_t*>(slice);
 
     uint32_t pad[NREG];
 #pragma unroll
@@ -248,8 +279,15 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
         const uint32_t hi = (sub * DPL + 2 * k + 1 < ndisp) ? 0u : kBig;
         pad[k] = lo | (hi << 16);
     }
+    // the no-write bias goes either on the lane's offset (aligned stores) or
+    // on each element's offset (unaligned ones), never on both: two biases
+    // would wrap back into range
+    uint32_t eoff[DPL];
+#pragma unroll
+    for (int e = 0; e < DPL; ++e) eoff[e] = (uint32_t)e + ((write && d0 + e < ndisp) ? 0u : kNoWrite);
 
-    // current pixel (x, y) and the look-ahead pixel of the prefetch
+    // first pixel of the line, the per-step stride of the volume offset and,
+    // for a diagonal, the stride of the step that wraps to the other border
     int x, y;
     if constexpr (KIND == kHorizontal) {
         y = lc;
@@ -258,20 +296,30 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
         x = lc;
         y = dy > 0 ? 0 : height - 1;
     }
+    const int32_t stride = (dy * width + dx) * ndisp;
+    const int32_t stride_wrap = (dy * width + dx - dx * width) * ndisp;
+    const int last_x = dx > 0 ? width - 1 : 0;        // a diagonal wraps after this column
     const int restart_x = dx > 0 ? 0 : width - 1;
-    int xa = x, ya = y, sa = 0;
-    auto step_pos = [&](int& px, int& py) {
-        px += dx;
-        py += dy;
+    const uint32_t off0 = ((uint32_t)y * (uint32_t)width + (uint32_t)x) * (uint32_t)ndisp + (uint32_t)d0;
+    uint32_t soff = off0 + ((U8 && ALIGNED && !write) ? kNoWrite : 0u);  // store side
+    uint32_t aoff = off0;                                       // prefetch side (cost bytes)
+    int xa = x, sa = 0;
+
+    // advance one step along the line; returns true when a diagonal wraps
+    auto advance = [&](uint32_t& off, int& px) {
         if constexpr (KIND == kDiagonal) {
-            px = (px == width) ? 0 : px;
-            px = (px < 0) ? width - 1 : px;
+            const bool wrap = px == last_x;
+            off += (uint32_t)(wrap ? stride_wrap : stride);
+            px = wrap ? restart_x : px + dx;
+            return wrap;
+        } else {
+            off += (uint32_t)stride;
+            return false;
         }
     };
     auto fetch = [&]() {
-        const CostVec<NREG> c = load_cost<NREG, ALIGNED>(
-            cost, ((uint32_t)ya * (uint32_t)width + (uint32_t)xa) * pix_bytes + (uint32_t)d0, d0, ndisp);
-        if (sa + 1 < nsteps) step_pos(xa, ya);     // stay on the last pixel past the end
+        const CostVec<NREG> c = load_cost<NREG, ALIGNED>(cost, aoff, d0, ndisp);
+        if (sa + 1 < nsteps) advance(aoff, xa);      // stay on the last pixel past the end
         ++sa;
         return c;
     };
@@ -283,6 +331,7 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
     uint32_t P[NREG];
 #pragma unroll
     for (int k = 0; k < NREG; ++k) P[k] = pad[k];
+    bool restart = false;                             // the line re-entered at the other border
 
     const int nchunks = (nsteps + K - 1) / K;
     for (int chunk = 0; chunk < nchunks; ++chunk) {
@@ -295,10 +344,11 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
         for (int j = 0; j < K; ++j) {
             const int s = chunk * K + j;
             if constexpr (KIND == kDiagonal) {
-                // a wrapped line restarts where it re-enters at the other border
-                const bool restart = s > 0 && x == restart_x;
+                // one step in a line's H wraps; skip the selects on the others
+                if (__builtin_amdgcn_ballot_w64(restart)) {
 #pragma unroll
-                for (int k = 0; k < NREG; ++k) P[k] = restart ? pad[k] : P[k];
+                    for (int k = 0; k < NREG; ++k) P[k] = restart ? pad[k] : P[k];
+                }
             }
             uint32_t Q[NREG];
             const uint32_t nxt0 = line_next<LPL>(P[0], kBig2, last_lane);
@@ -323,12 +373,12 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
             const uint32_t m = line_min<LPL>(min(mm & 0xFFFFu, mm >> 16));
             const uint32_t m2 = pk_splat(m);
 
-            if (write && s < nsteps)
-                store_out<NREG, ALIGNED, U8>(slice, ((uint32_t)y * (uint32_t)width + (uint32_t)x) * pix_bytes + (uint32_t)d0,
-                                             d0, ndisp, A, L);
+            if (s < nsteps) {
+                store_out<NREG, ALIGNED, U8>(rs, wide, soff, write, d0, ndisp, eoff, A, L);
+                restart = advance(soff, x);
+            }
 #pragma unroll
             for (int k = 0; k < NREG; ++k) P[k] = pk_sub(L[k], m2);
-            if (s + 1 < nsteps) step_pos(x, y);
         }
     }
 }
@@ -354,19 +404,21 @@ __device__ __forceinline__ void paths_block(const Frame& f, int lb) {
     const DirTask task = find_dir(lb, f.width, f.height, f.npaths, LH, LO, &block0, &di);
     const int wave_in_dir = (lb - block0) * kWaves + (int)(threadIdx.x >> 6);
     void* slice = f.slices + (size_t)di * f.slice_stride * (U8 ? 1 : 2);
+    // bytes of this path's slice: the range the buffer stores check
+    const uint32_t slice_bytes = (uint32_t)((size_t)f.width * f.height * f.ndisp);
     const uint32_t p1x2 = pk_splat((uint32_t)f.p1);
     const uint32_t p2x2 = pk_splat((uint32_t)f.p2);
     if (task.dy == 0) {
         __builtin_amdgcn_s_setprio(2);
-        run_lines<kHorizontal, NH, LH, KH, ALH, PDH, U8>(f.cost, slice, f.width, f.height, f.ndisp,
-                                                         p1x2, p2x2, task, wave_in_dir);
+        run_lines<kHorizontal, NH, LH, KH, ALH, PDH, U8>(f.cost, slice, slice_bytes, f.width, f.height,
+                                                         f.ndisp, p1x2, p2x2, task, wave_in_dir);
         __builtin_amdgcn_s_setprio(0);
     } else if (task.dx == 0) {
-        run_lines<kVertical, NO, LO, KO, ALO, PDO, U8>(f.cost, slice, f.width, f.height, f.ndisp,
-                                                       p1x2, p2x2, task, wave_in_dir);
+        run_lines<kVertical, NO, LO, KO, ALO, PDO, U8>(f.cost, slice, slice_bytes, f.width, f.height,
+                                                       f.ndisp, p1x2, p2x2, task, wave_in_dir);
     } else {
-        run_lines<kDiagonal, NO, LO, KO, ALO, PDO, U8>(f.cost, slice, f.width, f.height, f.ndisp,
-                                                       p1x2, p2x2, task, wave_in_dir);
+        run_lines<kDiagonal, NO, LO, KO, ALO, PDO, U8>(f.cost, slice, slice_bytes, f.width, f.height,
+                                                       f.ndisp, p1x2, p2x2, task, wave_in_dir);
     }
 }
 

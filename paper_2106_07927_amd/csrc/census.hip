@@ -134,7 +134,23 @@ __global__ __launch_bounds__(kThreads) void census_batch_kernel(WorkList wl) {
     }
 }
 
+// Both images of one frame in one launch: blockIdx.z selects the image.
+template <int RX, int RY>
+__global__ __launch_bounds__(kThreads) void census_pair_kernel(Frame f) {
+    __shared__ CensusTile<RX, RY> tile;
+    const bool right = blockIdx.z != 0;
+    census_tile<RX, RY>(tile, right ? f.right : f.left, f.width, f.height, f.pitch,
+                        right ? f.census_right : f.census_left, blockIdx.x, blockIdx.y);
+}
+
 }  // namespace
+
+hipError_t launch_census_pair(const Frame& f, hipStream_t stream) {
+    const dim3 grid(census_blocks_x(f.width), (f.height + kCensusTileH - 1) / kCensusTileH, 2);
+    if (f.win_w == 5 && f.win_h == 5) census_pair_kernel<2, 2><<<grid, kThreads, 0, stream>>>(f);
+    else census_pair_kernel<4, 3><<<grid, kThreads, 0, stream>>>(f);
+    return hipGetLastError();
+}
 
 hipError_t launch_census(const Frame& f, bool right, hipStream_t stream) {
     const dim3 grid(census_blocks_x(f.width), (f.height + kCensusTileH - 1) / kCensusTileH);

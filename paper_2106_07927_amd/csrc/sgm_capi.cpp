@@ -141,6 +141,27 @@ int32_t sgm_census(const uint8_t* img, int32_t width, int32_t height, int32_t pi
     return hip_status(sgm::launch_census(f, false, as_stream(stream)));
 }
 
+int32_t sgm_census_pair(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
+                        int32_t pitch_bytes, int32_t win_w, int32_t win_h,
+                        uint64_t* census_left_out, uint64_t* census_right_out, void* stream) {
+    if (!left || !right || !census_left_out || !census_right_out || bad_size(width, height) ||
+        pitch_bytes < width || census_left_out == census_right_out)
+        return SGM_ERR_ARG;
+    if (!((win_w == 5 && win_h == 5) || (win_w == 9 && win_h == 7))) return SGM_ERR_UNSUPPORTED;
+    if (!aligned(census_left_out, 8) || !aligned(census_right_out, 8)) return SGM_ERR_ALIGN;
+    sgm::Frame f{};
+    f.width = width;
+    f.height = height;
+    f.pitch = pitch_bytes;
+    f.win_w = win_w;
+    f.win_h = win_h;
+    f.left = left;
+    f.right = right;
+    f.census_left = census_left_out;
+    f.census_right = census_right_out;
+    return hip_status(sgm::launch_census_pair(f, as_stream(stream)));
+}
+
 int32_t sgm_cost(const uint64_t* census_left, const uint64_t* census_right, int32_t width,
                  int32_t height, int32_t ndisp, uint8_t* cost_out, void* stream) {
     if (!census_left || !census_right || !cost_out || bad_size(width, height)) return SGM_ERR_ARG;
@@ -380,8 +401,7 @@ int32_t sgm_disparity_exact_lr(const uint8_t* left, const uint8_t* right, int32_
             f.pitch = width;
             f.disp = flipped;
         }
-        if (e == hipSuccess) e = sgm::launch_census(f, false, s);
-        if (e == hipSuccess) e = sgm::launch_census(f, true, s);
+        if (e == hipSuccess) e = sgm::launch_census_pair(f, s);
         if (e == hipSuccess) e = sgm::launch_cost(f, s);
         if (e == hipSuccess) e = run_select(f, s);
     }

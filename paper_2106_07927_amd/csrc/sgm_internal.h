@@ -249,6 +249,7 @@ size_t aggregate_work_bytes(int width, int height, int ndisp, int npaths, int p2
 // (same window for census, same D for cost / paths / select).
 // ---------------------------------------------------------------------------
 hipError_t launch_census(const Frame& f, bool right, hipStream_t stream);
+hipError_t launch_census_pair(const Frame& f, hipStream_t stream);
 hipError_t launch_cost(const Frame& f, hipStream_t stream);
 hipError_t launch_ncc_cost(const uint8_t* left, const uint8_t* right, int width, int height,
                            int pitch, int win, int ndisp, uint8_t* cost, hipStream_t stream);

@@ -29,8 +29,8 @@ SGM_ERR_ALIGN = -3
 SGM_ERR_HIP = -4
 SGM_ERR_WORKSPACE = -5
 
-EXPORTS = ("sgm_census", "sgm_cost", "sgm_cost_ncc", "sgm_aggregate", "sgm_aggregate_work_bytes",
-           "sgm_wta_lrc", "sgm_wta_lrc_work_elems", "sgm_aggregate_select", "sgm_aggregate_select_work_bytes",
+EXPORTS = ("sgm_census", "sgm_census_pair", "sgm_cost", "sgm_cost_ncc", "sgm_aggregate",
+           "sgm_aggregate_work_bytes", "sgm_wta_lrc", "sgm_wta_lrc_work_elems", "sgm_aggregate_select", "sgm_aggregate_select_work_bytes",
            "sgm_aggregate_select_subpixel", "sgm_aggregate_select_subpixel_work_bytes",
            "sgm_disparity_exact_lr", "sgm_disparity_exact_lr_work_bytes",
            "sgm_batch_workspace_bytes", "sgm_batch_plan_create",
@@ -64,16 +64,21 @@ class SGMError(RuntimeError):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libsgm.so and declare its signatures (no GPU call is made)."""
+def load_library(path: Optional[str] = None):
+    """Load libsgm.so (or the library at `path`, kept for later calls) and
+    declare its signatures (no GPU call is made).  The default is LIB_PATH
+    as it stands at the first call."""
     global _lib
-    if _lib is not None and path == LIB_PATH:
+    if _lib is not None and (path is None or path == _lib._name):
         return _lib
+    if path is None:
+        path = LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run `python -m paper_2106_07927_amd.build`")
     lib = ctypes.CDLL(path)
     P, I32 = ctypes.c_void_p, ctypes.c_int32
     lib.sgm_census.argtypes = [P, I32, I32, I32, I32, I32, P, P]
+    lib.sgm_census_pair.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P]
     lib.sgm_cost.argtypes = [P, P, I32, I32, I32, P, P]
     lib.sgm_cost_ncc.argtypes = [P, P, I32, I32, I32, I32, I32, P, P]
     lib.sgm_cost_ncc.restype = I32
@@ -114,11 +119,10 @@ def load_library(path: str = LIB_PATH):
     lib.sgm_status_string.restype = ctypes.c_char_p
     lib.sgm_last_hip_error.argtypes = []
     lib.sgm_abi_version.argtypes = []
-    for name in ("sgm_census", "sgm_cost", "sgm_aggregate", "sgm_wta_lrc", "sgm_aggregate_select",
-                 "sgm_last_hip_error", "sgm_abi_version"):
+    for name in ("sgm_census", "sgm_census_pair", "sgm_cost", "sgm_aggregate", "sgm_wta_lrc",
+                 "sgm_aggregate_select", "sgm_last_hip_error", "sgm_abi_version"):
         getattr(lib, name).restype = I32
-    if path == LIB_PATH:
-        _lib = lib
+    _lib = lib
     return lib
 
 
@@ -174,6 +178,30 @@ def sgm_census(img: torch.Tensor, win_w: int, win_h: int, out: Optional[torch.Te
     _expect(out, torch.uint64, (h, w), "out")
     _check(load_library().sgm_census(_ptr(img), w, h, pitch, win_w, win_h, _ptr(out), _stream(stream)))
     return out
+
+
+def sgm_census_pair(left: torch.Tensor, right: torch.Tensor, win_w: int, win_h: int,
+                    out_left: Optional[torch.Tensor] = None,
+                    out_right: Optional[torch.Tensor] = None, width: Optional[int] = None,
+                    stream=None):
+    """Census of both images in one launch.  left, right: uint8 [H][pitch] of
+    one shape; returns (census_left, census_right), uint64 [H][W] each."""
+    for name, img in (("left", left), ("right", right)):
+        if img.dtype != torch.uint8 or img.dim() != 2:
+            raise ValueError(f"{name} must be a 2-D uint8 tensor")
+    if left.shape != right.shape or left.stride() != right.stride():
+        raise ValueError("left and right must have one shape and pitch")
+    h, pitch = left.shape
+    w = pitch if width is None else width
+    if out_left is None:
+        out_left = _empty((h, w), torch.uint64, left.device)
+    if out_right is None:
+        out_right = _empty((h, w), torch.uint64, left.device)
+    _expect(out_left, torch.uint64, (h, w), "out_left")
+    _expect(out_right, torch.uint64, (h, w), "out_right")
+    _check(load_library().sgm_census_pair(_ptr(left), _ptr(right), w, h, pitch, win_w, win_h,
+                                          _ptr(out_left), _ptr(out_right), _stream(stream)))
+    return out_left, out_right
 
 
 def sgm_cost(census_left: torch.Tensor, census_right: torch.Tensor, ndisp: int,
@@ -345,8 +373,8 @@ class Params:
 
 class StereoSGM:
     """Device buffers for one frame shape, reused across frames.  run()
-    enqueues census (x2), cost and the streamlined sgm_aggregate_select on one
-    stream; with fused=False it enqueues the four calls sgm_census (x2),
+    enqueues sgm_census_pair, sgm_cost and the streamlined sgm_aggregate_select
+    on one stream; with fused=False it enqueues the four calls sgm_census (x2),
     sgm_cost, sgm_aggregate, sgm_wta_lrc instead (same bits, S_bar kept in
     self.agg)."""
 
@@ -370,8 +398,14 @@ class StereoSGM:
 
     def run(self, left: torch.Tensor, right: torch.Tensor, stream=None) -> torch.Tensor:
         p = self.params
-        sgm_census(left, p.win_w, p.win_h, out=self.census_left, width=self.width, stream=stream)
-        sgm_census(right, p.win_w, p.win_h, out=self.census_right, width=self.width, stream=stream)
+        if self.fused and left.shape == right.shape and left.stride() == right.stride():
+            sgm_census_pair(left, right, p.win_w, p.win_h, out_left=self.census_left,
+                            out_right=self.census_right, width=self.width, stream=stream)
+        else:
+            sgm_census(left, p.win_w, p.win_h, out=self.census_left, width=self.width,
+                       stream=stream)
+            sgm_census(right, p.win_w, p.win_h, out=self.census_right, width=self.width,
+                       stream=stream)
         sgm_cost(self.census_left, self.census_right, p.ndisp, out=self.cost, stream=stream)
         if self.fused:
             sgm_aggregate_select(self.cost, p.npaths, p.p1, p.p2, p.lr_tolerance, p.median3x3,

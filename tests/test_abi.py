@@ -64,6 +64,19 @@ def test_census_validation(lib):
     assert f(P(FAKE), 64, 64, 64, 5, 5, P(FAKE + 4), P(NULL)) == ALIGN
 
 
+def test_census_pair_validation(lib):
+    f = lib.sgm_census_pair
+    A, B = FAKE, FAKE + 0x1000
+    assert f(P(NULL), P(FAKE), 64, 64, 64, 9, 7, P(A), P(B), P(NULL)) == ARG
+    assert f(P(FAKE), P(NULL), 64, 64, 64, 9, 7, P(A), P(B), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 64, 64, 64, 9, 7, P(NULL), P(B), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 64, 64, 64, 9, 7, P(A), P(A), P(NULL)) == ARG    # one buffer twice
+    assert f(P(FAKE), P(FAKE), 64, 64, 63, 9, 7, P(A), P(B), P(NULL)) == ARG    # pitch < width
+    assert f(P(FAKE), P(FAKE), 0, 64, 64, 9, 7, P(A), P(B), P(NULL)) == ARG
+    assert f(P(FAKE), P(FAKE), 64, 64, 64, 7, 9, P(A), P(B), P(NULL)) == UNSUP
+    assert f(P(FAKE), P(FAKE), 64, 64, 64, 5, 5, P(A), P(B + 4), P(NULL)) == ALIGN
+
+
 def test_cost_validation(lib):
     f = lib.sgm_cost
     assert f(P(NULL), P(FAKE), 8, 8, 16, P(FAKE), P(NULL)) == ARG

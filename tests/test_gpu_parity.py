@@ -76,6 +76,21 @@ def test_census_pitch(dev):
     np.testing.assert_array_equal(out, oracle.census(np.ascontiguousarray(img[:, :67]), 9, 7))
 
 
+@pytest.mark.parametrize("win", [(5, 5), (9, 7)])
+@pytest.mark.parametrize("w,h,width", [(1, 1, None), (7, 2, None), (65, 33, None), (80, 20, 67),
+                                       (1242, 375, None)])
+def test_census_pair_parity(dev, win, w, h, width):
+    """One launch for both images: each output equals the oracle's census of
+    its own image (pitched inputs included)."""
+    from paper_2106_07927_amd import sgm
+    say(f"census pair {w}x{h} width={width} win{win}")
+    left, right = datagen.random_images(w, h, seed=w * 7 + h)
+    cl, cr = sgm.sgm_census_pair(to_dev(left, dev), to_dev(right, dev), *win, width=width)
+    ww = w if width is None else width
+    np.testing.assert_array_equal(host(cl), oracle.census(np.ascontiguousarray(left[:, :ww]), *win))
+    np.testing.assert_array_equal(host(cr), oracle.census(np.ascontiguousarray(right[:, :ww]), *win))
+
+
 # ------------------------------------------------------------------ cost ---
 @pytest.mark.parametrize("nd", [1, 3, 4, 16, 64, 96, 128, 256])
 @pytest.mark.parametrize("w", [1, 7, 65, 321])
