@@ -10,14 +10,16 @@
 // direction; the long horizontal chains, which bound the launch, get priority.
 //
 // Lanes.  A line is owned by LPL consecutive lanes; each lane keeps 2*NREG
-// disparities of the path vector as packed uint16 pairs.  The state is kept
-// normalised, N = L' - min_d L', so one step reads
-//     L(d) = C(d) + min(N(d), min(N(d-1), N(d+1)) + P1, P2);
-// min(N(d-1), N(d+1)) comes from Q_k = min(P_k, P_k+1) and one alignbit per
-// register, with one DPP lane shift each way per step; min_d L is a
-// v_pk_min_u16 tree plus a DPP / permlane all-reduce over the line's lanes.
-// Disparities beyond D (padding) hold 0x7FFF: never a minimum, and as a
-// neighbour never below the P2 term.
+// disparities of the path vector as packed uint16 pairs.  The state is the
+// previous pixel's path vector L' (each value C + A <= 255 + P2), and one
+// step reads
+//     L(d) = C(d) + min(X(d), m' + P2) - m',
+//     X(d) = min(L'(d), min(L'(d-1), L'(d+1)) + P1),  m' = min_d L'(d);
+// min(L'(d-1), L'(d+1)) comes from Q_k = min(L'_k, L'_k+1) and one alignbit
+// per register, with one DPP lane shift each way per step; m' is a
+// v_pk_min_u16 tree plus a DPP / permlane all-reduce over the line's lanes,
+// which runs beside X instead of ahead of it.  Disparities beyond D (padding)
+// hold 0x7FFF: never a minimum, and as a neighbour never below m' + P2.
 //
 // Memory.  On this GPU family one counter tracks both loads and stores, so a
 // loop that prefetches while it stores would wait for every store each step.
@@ -195,16 +197,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(void* base, uint32_
 }
 
 // Writes the step's output of one lane: penalty bytes through the slice's
-// buffer resource (U8; `off` is the biased byte offset of the lane's first
-// disparity, `eoff` the per-element offsets of the unaligned form), or path
-// values (uint16) through a plain pointer, guarded by `write`.
+// buffer resource (U8; `off` is the byte offset of the lane's first
+// disparity, biased for a lane that never writes, `eoff` the per-element
+// offsets of the unaligned form, and `past` = kNoWrite on the steps after a
+// line's end, OR-ed in last so that it cannot cancel a bias), or path values
+// (uint16) through a plain pointer, guarded by `write` and `past`.
 template <int NREG, bool ALIGNED, bool U8>
 __device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, uint16_t* __restrict__ wide,
-                                          uint32_t off, bool write, int d0, int ndisp,
+                                          uint32_t off, uint32_t past, bool write, int d0, int ndisp,
                                           const uint32_t (&eoff)[2 * NREG],
                                           const uint32_t (&A)[NREG], const uint32_t (&L)[NREG]) {
     if constexpr (U8) {
         if constexpr (ALIGNED) {
+            off |= past;
             if constexpr (NREG == 1) {
                 __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__builtin_amdgcn_perm(0u, A[0], 0x0c0c0200u),
                                                       rs, off, 0, 0);
@@ -230,10 +235,10 @@ __device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, uint16_t* _
 #pragma unroll
             for (int e = 0; e < 2 * NREG; ++e)
                 __builtin_amdgcn_raw_buffer_store_b8((uint8_t)((e & 1) ? (A[e >> 1] >> 16) : A[e >> 1]), rs,
-                                                     off + eoff[e], 0, 0);
+                                                     (off + eoff[e]) | past, 0, 0);
         }
     } else {
-        if (!write) return;
+        if (!write || past) return;
         uint16_t* p = wide + off;
         if constexpr (ALIGNED) {
             uint32_t* q = reinterpret_cast<uint32_t*>(p);
@@ -328,9 +333,16 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
 #pragma unroll
     for (int j = 0; j < K; ++j) nxt[j] = fetch();
 
-    uint32_t P[NREG];
+    // Path values of the previous pixel, L' (not normalised: every valid one
+    // is C + A <= 255 + P2, padding holds 0x7FFF).  The line's minimum m' is
+    // needed only at the end of a step,
+    //     A(d) = min(X(d), m' + P2) - m',  X(d) = min(L'(d), min(L'(d-1), L'(d+1)) + P1),
+    // so the cross-lane reduction for m' runs beside the neighbour terms X
+    // rather than ahead of them on the step's dependency chain.  At a line's
+    // start (and a diagonal's restart) L' = padding: m' = 0 and A = 0.
+    uint32_t Lp[NREG];
 #pragma unroll
-    for (int k = 0; k < NREG; ++k) P[k] = pad[k];
+    for (int k = 0; k < NREG; ++k) Lp[k] = pad[k];
     bool restart = false;                             // the line re-entered at the other border
 
     const int nchunks = (nsteps + K - 1) / K;
@@ -347,38 +359,47 @@ __device__ __forceinline__ void run_lines(const uint8_t* __restrict__ cost, void
                 // one step in a line's H wraps; skip the selects on the others
                 if (__builtin_amdgcn_ballot_w64(restart)) {
 #pragma unroll
-                    for (int k = 0; k < NREG; ++k) P[k] = restart ? pad[k] : P[k];
+                    for (int k = 0; k < NREG; ++k) Lp[k] = restart ? pad[k] : Lp[k];
                 }
             }
-            uint32_t Q[NREG];
-            const uint32_t nxt0 = line_next<LPL>(P[0], kBig2, last_lane);
+            // m' over the line
+            uint32_t mm = Lp[0];
 #pragma unroll
-            for (int k = 0; k + 1 < NREG; ++k) Q[k] = pk_min(P[k], P[k + 1]);
-            Q[NREG - 1] = pk_min(P[NREG - 1], nxt0);
-            const uint32_t qprev = line_prev<LPL>(Q[NREG - 1], P[0], first_lane);
+            for (int k = 1; k < NREG; ++k) mm = pk_min(mm, Lp[k]);
+            const uint32_t m = line_min<LPL>(min(mm & 0xFFFFu, mm >> 16));
 
+            // X(d), independent of m'
+            uint32_t Q[NREG];
+            const uint32_t nxt0 = line_next<LPL>(Lp[0], kBig2, last_lane);
+#pragma unroll
+            for (int k = 0; k + 1 < NREG; ++k) Q[k] = pk_min(Lp[k], Lp[k + 1]);
+            Q[NREG - 1] = pk_min(Lp[NREG - 1], nxt0);
+            const uint32_t qprev = line_prev<LPL>(Q[NREG - 1], Lp[0], first_lane);
+            uint32_t X[NREG];
+#pragma unroll
+            for (int k = 0; k < NREG; ++k)
+                X[k] = pk_min(pk_add(pk_shift_in(Q[k], k == 0 ? qprev : Q[k - 1]), p1x2), Lp[k]);
+
+            const uint32_t m2 = pk_splat(m);
+            const uint32_t cap = pk_add(m2, p2x2);
             uint32_t A[NREG], L[NREG];
 #pragma unroll
             for (int k = 0; k < NREG; ++k) {
-                uint32_t a = pk_add(pk_shift_in(Q[k], k == 0 ? qprev : Q[k - 1]), p1x2);
-                a = pk_min(pk_min(a, P[k]), p2x2);
+                const uint32_t a = pk_sub(pk_min(X[k], cap), m2);
                 A[k] = a;
                 uint32_t l = pk_add(a, cost_pair<NREG>(cur[j], k));
                 if constexpr (PADDED) l = pk_max(l, pad[k]);
                 L[k] = l;
             }
-            uint32_t mm = L[0];
-#pragma unroll
-            for (int k = 1; k < NREG; ++k) mm = pk_min(mm, L[k]);
-            const uint32_t m = line_min<LPL>(min(mm & 0xFFFFu, mm >> 16));
-            const uint32_t m2 = pk_splat(m);
 
-            if (s < nsteps) {
-                store_out<NREG, ALIGNED, U8>(rs, wide, soff, write, d0, ndisp, eoff, A, L);
-                restart = advance(soff, x);
-            }
+            // every step stores, past a line's end out of range: a store
+            // count the compiler can see lets each chunk wait for its loads
+            // only, not for the stores issued after them
+            store_out<NREG, ALIGNED, U8>(rs, wide, soff, s < nsteps ? 0u : kNoWrite, write, d0, ndisp,
+                                         eoff, A, L);
+            restart = advance(soff, x);
 #pragma unroll
-            for (int k = 0; k < NREG; ++k) P[k] = pk_sub(L[k], m2);
+            for (int k = 0; k < NREG; ++k) Lp[k] = L[k];
         }
     }
 }
