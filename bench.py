@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the served trace (0 skips the served form)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--max-streams", type=int, default=8,
+                    help="largest frames-in-flight count timed (1: single-stream modes only, "
+                         "so that a kernel trace sees no overlapping frames)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the path, run a plain device copy of this many MiB five "
                          "times (the known-size kernel that scales HBM counter readings)")
@@ -60,8 +63,8 @@ def parse():
 # entry holds only for the kernel sources whose digest it names; for any other
 # sources the figure is reported as null.
 TRAFFIC = {
-    "sgm_aggregate_select": {"sources": "ec75dfd9ef27003c", "bytes": 1488296733},
-    "sgm_aggregate": {"sources": "ec75dfd9ef27003c", "bytes": 1586737376},
+    "sgm_aggregate_select": {"sources": "0441a872ee804f1a", "bytes": 1486373597},
+    "sgm_aggregate": {"sources": "0441a872ee804f1a", "bytes": 1588120776},
 }
 
 KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "wta_lrc.hip", "sgm_internal.h")
@@ -373,7 +376,7 @@ def main():
         del engs
         return ms
 
-    ms_streams = {n: timed_streams(n) for n in (2, 3, 4, 6, 8)}
+    ms_streams = {n: timed_streams(n) for n in (2, 3, 4, 6, 8) if n <= args.max_streams}
     modes = {"eager": ms_eager, "hipGraph replay": ms_graph}
     modes.update({f"{n} streams": v for n, v in ms_streams.items()})
     launch_mode = min(modes, key=modes.get)

@@ -102,7 +102,7 @@ def _a256(b: int) -> int:
 
 def slot_bytes(spec: StreamSpec, npaths: int, p2: int) -> int:
     """Device bytes of one slot (the buffers of one StereoSGM): inputs,
-    census x2, cost, the workspace of the streamlined aggregation (path
+    both census maps, cost, the workspace of the streamlined aggregation (path
     slices, S_bar only where the fused selection does not apply, D^R keys,
     D^L) and the two disparity maps."""
     n = spec.width * spec.height
