@@ -15,6 +15,11 @@
 // Every stage is one persistent launch that walks its work list of
 // (frame, block) items; the blocks of a frame are exactly those of the
 // single-frame call, so each frame's results are bit-identical to it.
+// Only frames below kSmallPixels go through these work lists: there a
+// stage's blocks of many frames fill the GPU where one frame's would not.
+// A larger frame already fills it and runs faster through the single-frame
+// kernels, so the graph launches those for it, on one of kChains streams
+// forked and joined inside the graph.
 // Running the plan is one hipGraphLaunch.
 #include <hip/hip_runtime.h>
 
@@ -87,6 +92,11 @@ int stage_blocks(Stage st, const Frame& f) {
         default: return 0;
     }
 }
+
+constexpr int kChains = 4;
+constexpr long kSmallPixels = 100000;
+
+bool small_frame(const Frame& f) { return (long)f.width * f.height < kSmallPixels; }
 
 // One launch: a stage over a group of frames (indices into the frame table).
 struct Launch {
@@ -164,27 +174,30 @@ size_t build_layout(const sgm_pair* pairs, int32_t n, const sgm_params* p, const
         off += l.total;
         frames->push_back(f);
     }
-    // launch groups, in stage order
-    std::vector<int> all(n);
-    for (int i = 0; i < n; ++i) all[i] = i;
-    std::map<int, std::vector<int>> by_d;
-    std::map<std::pair<int, int>, std::vector<int>> by_dv;
-    std::vector<int> unfused;
-    for (int i = 0; i < n; ++i) {
-        by_d[(*frames)[i].ndisp].push_back(i);
-        by_dv[{(*frames)[i].ndisp, (*frames)[i].variant}].push_back(i);
-        if (!fused_select_supported((*frames)[i].ndisp, p->npaths, p->p2)) unfused.push_back(i);
+    // work-list launch groups over the small frames, in stage order
+    std::vector<int> all;
+    for (int i = 0; i < n; ++i)
+        if (small_frame((*frames)[i])) all.push_back(i);
+    if (!all.empty()) {
+        std::map<int, std::vector<int>> by_d;
+        std::map<std::pair<int, int>, std::vector<int>> by_dv;
+        std::vector<int> unfused;
+        for (int i : all) {
+            by_d[(*frames)[i].ndisp].push_back(i);
+            by_dv[{(*frames)[i].ndisp, (*frames)[i].variant}].push_back(i);
+            if (!fused_select_supported((*frames)[i].ndisp, p->npaths, p->p2)) unfused.push_back(i);
+        }
+        launches->push_back({kCensus, 0, 0, all});
+        for (auto& kv : by_d) launches->push_back({kCost, kv.first, 0, kv.second});
+        for (auto& kv : by_dv) launches->push_back({kPaths, kv.first.first, kv.first.second, kv.second});
+        if (!unfused.empty()) launches->push_back({kMerge, 0, 0, unfused});
+        launches->push_back({kFill, 0, 0, all});
+        for (auto& kv : by_d) {
+            const bool fused = fused_select_supported(kv.first, p->npaths, p->p2);
+            launches->push_back({fused ? kFused : kSelect, kv.first, 0, kv.second});
+        }
+        launches->push_back({kMedian, 0, 0, all});
     }
-    launches->push_back({kCensus, 0, 0, all});
-    for (auto& kv : by_d) launches->push_back({kCost, kv.first, 0, kv.second});
-    for (auto& kv : by_dv) launches->push_back({kPaths, kv.first.first, kv.first.second, kv.second});
-    if (!unfused.empty()) launches->push_back({kMerge, 0, 0, unfused});
-    launches->push_back({kFill, 0, 0, all});
-    for (auto& kv : by_d) {
-        const bool fused = fused_select_supported(kv.first, p->npaths, p->p2);
-        launches->push_back({fused ? kFused : kSelect, kv.first, 0, kv.second});
-    }
-    launches->push_back({kMedian, 0, 0, all});
     // tables: one frame table per launch (frames of the group, in order) and
     // its block starts
     *tables_off = off;
@@ -293,30 +306,83 @@ int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n, const sgm_params
 
     sgm_plan* plan = new sgm_plan();
     plan->nframes = n;
+    // streams of the graph: the work lists on the first; the large frames,
+    // by descending volume, each to the stream with the least volume so far
+    std::vector<int> large;
+    for (int i = 0; i < n; ++i)
+        if (!small_frame(frames[i])) large.push_back(i);
+    auto vol = [&](int i) { return (double)frames[i].width * frames[i].height * frames[i].ndisp; };
+    std::stable_sort(large.begin(), large.end(), [&](int a, int b) { return vol(a) > vol(b); });
+    const int nchains = std::max(1, std::min<int>(kChains, (int)large.size() + (launches.empty() ? 0 : 1)));
+    std::vector<std::vector<int>> chain_frames(nchains);
+    std::vector<double> load(nchains, 0.0);
+    if (!launches.empty()) {
+        for (int i = 0; i < n; ++i)
+            if (small_frame(frames[i])) load[0] += vol(i);
+    }
+    for (int i : large) {
+        const int c = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        chain_frames[c].push_back(i);
+        load[c] += vol(i);
+    }
+    std::vector<hipStream_t> side(nchains, nullptr);
+    std::vector<hipEvent_t> ev;                     // fork and joins
+    auto new_event = [&](hipEvent_t* out) {
+        hipError_t r = hipEventCreateWithFlags(out, hipEventDisableTiming);
+        if (r == hipSuccess) ev.push_back(*out);
+        return r;
+    };
     e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
+    for (int c = 0; c < nchains && e == hipSuccess; ++c) e = hipStreamCreateWithFlags(&side[c], hipStreamNonBlocking);
+    hipEvent_t fork = nullptr;
+    if (e == hipSuccess) e = new_event(&fork);
     if (e == hipSuccess) e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipStream_t s = plan->capture_stream;
-        for (const Launch& L : launches) {
-            hipError_t le = hipSuccess;
+        hipError_t ce = hipEventRecord(fork, plan->capture_stream);
+        for (int c = 0; c < nchains && ce == hipSuccess; ++c) ce = hipStreamWaitEvent(side[c], fork, 0);
+        for (size_t k = 0; k < launches.size() && ce == hipSuccess; ++k) {
+            const Launch& L = launches[k];
+            hipStream_t s = side[0];
             switch (L.stage) {
-                case kCensus: le = launch_census_batch(L.wl, params->win_w, params->win_h, s); break;
-                case kCost: le = launch_cost_batch(L.wl, L.ndisp, s); break;
-                case kPaths: le = launch_paths_batch(L.wl, L.ndisp, params->npaths, params->p2, L.variant, s); break;
-                case kMerge: le = launch_merge_batch(L.wl, params->npaths, params->p2, s); break;
-                case kFill: le = launch_fill_keys_batch(L.wl, s); break;
-                case kSelect: le = launch_select_batch(L.wl, L.ndisp, s); break;
-                case kFused:
-                    le = launch_select_fused_batch(L.wl, L.ndisp, params->npaths, params->p2, s);
+                case kCensus: ce = launch_census_batch(L.wl, params->win_w, params->win_h, s); break;
+                case kCost: ce = launch_cost_batch(L.wl, L.ndisp, s); break;
+                case kPaths:
+                    ce = launch_paths_batch(L.wl, L.ndisp, params->npaths, params->p2, L.variant, s);
                     break;
-                case kMedian: le = launch_median_batch(L.wl, s); break;
+                case kMerge: ce = launch_merge_batch(L.wl, params->npaths, params->p2, s); break;
+                case kFill: ce = launch_fill_keys_batch(L.wl, s); break;
+                case kSelect: ce = launch_select_batch(L.wl, L.ndisp, s); break;
+                case kFused: ce = launch_select_fused_batch(L.wl, L.ndisp, params->npaths, params->p2, s); break;
+                case kMedian: ce = launch_median_batch(L.wl, s); break;
                 default: break;
             }
-            if (le != hipSuccess && e == hipSuccess) e = le;
         }
-        hipError_t ce = hipStreamEndCapture(plan->capture_stream, &plan->graph);
+        for (int c = 0; c < nchains && ce == hipSuccess; ++c) {
+            hipStream_t s = side[c];
+            for (int i : chain_frames[c]) {
+                const Frame& f = frames[i];
+                if (ce == hipSuccess) ce = launch_census_pair(f, s);
+                if (ce == hipSuccess) ce = launch_cost(f, s);
+                if (ce != hipSuccess) break;
+                if (fused_select_supported(f.ndisp, f.npaths, f.p2)) {
+                    ce = launch_aggregate_select(f, s);
+                } else {
+                    ce = launch_aggregate(f, s);
+                    if (ce == hipSuccess) ce = launch_wta_lrc(f, s);
+                }
+            }
+            hipEvent_t je = nullptr;
+            if (ce == hipSuccess) ce = new_event(&je);
+            if (ce == hipSuccess) ce = hipEventRecord(je, s);
+            if (ce == hipSuccess) ce = hipStreamWaitEvent(plan->capture_stream, je, 0);
+        }
         if (e == hipSuccess) e = ce;
+        hipError_t ee = hipStreamEndCapture(plan->capture_stream, &plan->graph);
+        if (e == hipSuccess) e = ee;
     }
+    for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    for (hipStream_t x : side)
+        if (x) (void)hipStreamDestroy(x);
     if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         sgm_batch_plan_destroy(plan);
