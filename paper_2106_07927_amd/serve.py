@@ -291,8 +291,11 @@ class GpuBackend:
         torch = self.torch
         torch.cuda.synchronize()
         self.t0_event = torch.cuda.Event(enable_timing=True)
-        self.t0 = time.perf_counter()
         self.t0_event.record()
+        # the host clock starts once the event's timestamp is taken, so that
+        # device completion times and host arrival times share one origin
+        self.t0_event.synchronize()
+        self.t0 = time.perf_counter()
 
     def now(self):
         return time.perf_counter() - self.t0
