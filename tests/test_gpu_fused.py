@@ -178,3 +178,32 @@ def test_graph_replays_match_eager(dev):
                      oracle.Params(win_w=9, win_h=7, ndisp=nd, npaths=8, p1=10, p2=120,
                                    lr_tolerance=1, median3x3=True))
     np.testing.assert_array_equal(eng.disp.cpu().numpy(), ref["disp"])
+
+
+def test_frames_in_flight_on_streams(dev):
+    """Consecutive frames round-robin over engines on their own streams (the
+    bench's frames-in-flight mode): every frame equals its oracle result."""
+    import torch
+    from paper_2106_07927_amd import sgm
+    say("frames in flight, 3 streams")
+    w, h, nd = 320, 96, 64
+    prm = sgm.Params(win_w=9, win_h=7, ndisp=nd, npaths=8, p1=10, p2=120, lr_tolerance=1,
+                     median3x3=True)
+    pairs = [datagen.make_pair(w, h, nd, seed=700 + i, planes=(3, 5)) for i in range(6)]
+    ins = [(to_dev(p["left"], dev), to_dev(p["right"], dev)) for p in pairs]
+    engs = [sgm.StereoSGM(w, h, prm, device=dev) for _ in range(3)]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(3)]
+    torch.cuda.synchronize()                   # inputs were copied on the default stream
+    outs = [None] * len(pairs)
+    for rnd in range(2):
+        for i in range(rnd * 3, rnd * 3 + 3):
+            k = i % 3
+            engs[k].run(*ins[i], stream=streams[k])
+        torch.cuda.synchronize()
+        for i in range(rnd * 3, rnd * 3 + 3):
+            outs[i] = engs[i % 3].disp.cpu().numpy()
+    for i, p in enumerate(pairs):
+        ref = oracle.run(p["left"], p["right"],
+                         oracle.Params(win_w=9, win_h=7, ndisp=nd, npaths=8, p1=10, p2=120,
+                                       lr_tolerance=1, median3x3=True))
+        np.testing.assert_array_equal(outs[i], ref["disp"])
