@@ -292,6 +292,13 @@ __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, con
     const int nblk = tpx * ndisp / 16;             // <= 512
     uint4 c[2];
     uint4 a[2][NP];
+    // the slices are read once: nontemporal loads stream them past the
+    // caches (measured 123 -> 83 us at 1242x375, D = 128, 8 paths)
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    auto stream_load = [](const uint8_t* p) {
+        const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    };
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         if (256 * i >= nblk) break;                // uniform: small D fits in one pass
@@ -299,7 +306,7 @@ __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, con
         c[i] = *reinterpret_cast<const uint4*>(f.cost + e);
 #pragma unroll
         for (int r = 0; r < NP; ++r)
-            a[i][r] = *reinterpret_cast<const uint4*>(f.slices + (size_t)r * f.slice_stride + e);
+            a[i][r] = stream_load(f.slices + (size_t)r * f.slice_stride + e);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
