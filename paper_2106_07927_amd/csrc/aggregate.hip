@@ -475,7 +475,7 @@ __device__ __forceinline__ void merge_u8_block(const Frame& f, int lb) {
         const uint4 c = reinterpret_cast<const uint4*>(cost)[i];
         uint4 a[NP];
 #pragma unroll
-        for (int r = 0; r < NP; ++r) a[r] = reinterpret_cast<const uint4*>(slices + (size_t)r * f.slice_stride)[i];
+        for (int r = 0; r < NP; ++r) a[r] = load_once16(slices + (size_t)r * f.slice_stride + 16 * i);
         uint32_t s[8];
         merge16<NP, PAIR>(c, a, s);
         reinterpret_cast<uint4*>(agg)[2 * i] = make_uint4(s[0], s[1], s[2], s[3]);
@@ -499,9 +499,9 @@ __device__ __forceinline__ void merge_u16_block(const Frame& f, int lb) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const size_t i = e0 / 8 + h;
-            uint4 s = reinterpret_cast<const uint4*>(slices)[i];
+            uint4 s = load_once16(slices + 8 * i);
             for (int r = 1; r < f.npaths; ++r) {
-                const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * f.slice_stride)[i];
+                const uint4 a = load_once16(slices + (size_t)r * f.slice_stride + 8 * i);
                 s.x = pk_add(s.x, a.x);
                 s.y = pk_add(s.y, a.y);
                 s.z = pk_add(s.z, a.z);

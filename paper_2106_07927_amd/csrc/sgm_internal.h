@@ -33,6 +33,15 @@ __device__ __forceinline__ uint32_t pk_shift_in(uint32_t a, uint32_t b) {
 }
 __host__ __device__ __forceinline__ uint32_t pk_splat(uint32_t v16) { return v16 | (v16 << 16); }
 
+// 16 bytes that the path reads exactly once (penalty slices, S_bar): a
+// nontemporal load streams them past the caches, which keeps the lines that
+// are read again (the cost volume) resident.
+__device__ __forceinline__ uint4 load_once16(const void* p) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // ---------------------------------------------------------------------------
 // Path sum of 16 consecutive volume elements (Eq. sgm_path_aggr) from uint8
 // penalty slices: S = NP * C + sum_r A_r, with A_r = L_r - C in [0, P2].

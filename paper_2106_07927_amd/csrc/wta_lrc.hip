@@ -47,12 +47,14 @@ __device__ __forceinline__ RawVals<EPL> load_vals(const uint16_t* __restrict__ a
                                                   int d0, int ndisp) {
     RawVals<EPL> r;
     const uint16_t* p = agg + pix * ndisp + (d0 < ndisp ? d0 : 0);
+    // S_bar is read once: nontemporal loads
     if constexpr (VEC && EPL == 1) {
-        r.w[0] = *p;
+        r.w[0] = __builtin_nontemporal_load(p);
     } else if constexpr (VEC && EPL == 2) {
-        r.w[0] = *reinterpret_cast<const uint32_t*>(p);
+        r.w[0] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
     } else if constexpr (VEC && EPL == 4) {
-        const uint2 w = *reinterpret_cast<const uint2*>(p);
+        typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+        const v2u w = __builtin_nontemporal_load(reinterpret_cast<const v2u*>(p));
         r.w[0] = w.x;
         r.w[1] = w.y;
     } else {
@@ -292,13 +294,8 @@ __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, con
     const int nblk = tpx * ndisp / 16;             // <= 512
     uint4 c[2];
     uint4 a[2][NP];
-    // the slices are read once: nontemporal loads stream them past the
-    // caches (measured 123 -> 83 us at 1242x375, D = 128, 8 paths)
-    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-    auto stream_load = [](const uint8_t* p) {
-        const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
-        return make_uint4(v.x, v.y, v.z, v.w);
-    };
+    // the slices are read once (nontemporal loads: 123 -> 83 us at
+    // 1242x375, D = 128, 8 paths); the cost volume keeps cached loads
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         if (256 * i >= nblk) break;                // uniform: small D fits in one pass
@@ -306,7 +303,7 @@ __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, con
         c[i] = *reinterpret_cast<const uint4*>(f.cost + e);
 #pragma unroll
         for (int r = 0; r < NP; ++r)
-            a[i][r] = stream_load(f.slices + (size_t)r * f.slice_stride + e);
+            a[i][r] = load_once16(f.slices + (size_t)r * f.slice_stride + e);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
