@@ -18,8 +18,8 @@
 // Only frames below kSmallPixels go through these work lists: there a
 // stage's blocks of many frames fill the GPU where one frame's would not.
 // A larger frame already fills it and runs faster through the single-frame
-// kernels, so the graph launches those for it, on one of kChains streams
-// forked and joined inside the graph.
+// kernels, so the graph launches those for it, on kChains streams forked and
+// joined inside the graph.
 // Running the plan is one hipGraphLaunch.
 #include <hip/hip_runtime.h>
 
@@ -93,7 +93,10 @@ int stage_blocks(Stage st, const Frame& f) {
     }
 }
 
-constexpr int kChains = 4;
+// Streams for the large frames inside the graph.  Frames in flight on 2-4
+// streams measured up to 3 % slower than one stream on the 64-pair mix once
+// the selection stopped being bandwidth-bound next to the path pass.
+constexpr int kChains = 1;
 constexpr long kSmallPixels = 100000;
 
 bool small_frame(const Frame& f) { return (long)f.width * f.height < kSmallPixels; }
