@@ -3,11 +3,13 @@ simulated camera streams on one GPU.
 
 * Requests arrive per stream (Poisson traces from datagen.poisson_arrivals).
 * Each stream owns slots: resident device buffer sets (inputs, every
-  intermediate of the four ABI calls, the disparity output).  A slot is
-  allocated the first time the stream needs one and then reused for every
-  later frame of that stream; slots of all streams together stay under an
-  HBM budget; when a stream needs a slot that does not fit, an idle slot of
-  another stream is released (least recently used first).  A frame is
+  intermediate of the path, the disparity outputs).  A slot is carved the
+  first time the stream needs one and then reused for every later frame of
+  that stream.  All slots live in one device arena of the HBM budget's size,
+  allocated once: the budget is the memory the server holds, not a count.
+  When a stream needs a slot that does not fit, idle slots of other streams
+  are released back to the arena (least recently used first) -- no device
+  allocation or free happens while serving.  A frame is
   admitted as soon as one of its stream's slots is idle (or a new one fits
   the budget) and a HIP stream of the pool is free,
   so frames that arrive while others run start at once and overlap with them
@@ -100,17 +102,65 @@ def _a256(b: int) -> int:
     return (b + 255) // 256 * 256
 
 
+class Arena:
+    """First-fit allocator over [0, capacity) in 256-byte units, with
+    coalescing of released ranges.  Host bookkeeping only; GpuBackend maps
+    its offsets onto one device buffer."""
+
+    ALIGN = 256
+
+    def __init__(self, capacity: int):
+        self.capacity = capacity // self.ALIGN * self.ALIGN
+        self.free = [(0, self.capacity)]         # sorted, disjoint (offset, size)
+        self.used = 0
+
+    @classmethod
+    def round(cls, nbytes: int) -> int:
+        return (max(1, nbytes) + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        need = self.round(nbytes)
+        for i, (off, size) in enumerate(self.free):
+            if size >= need:
+                if size == need:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + need, size - need)
+                self.used += need
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int):
+        size = self.round(nbytes)
+        self.used -= size
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        self.free.insert(i, (off, size))
+        # merge with the neighbours
+        if i + 1 < len(self.free) and off + size == self.free[i + 1][0]:
+            self.free[i] = (off, size + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    def largest_free(self) -> int:
+        return max((size for _, size in self.free), default=0)
+
+
 def slot_bytes(spec: StreamSpec, npaths: int, p2: int) -> int:
-    """Device bytes of one slot (the buffers of one StereoSGM): inputs,
-    both census maps, cost, the workspace of the streamlined aggregation (path
-    slices, S_bar only where the fused selection does not apply, D^R keys,
-    D^L) and the two disparity maps."""
+    """Device bytes of one slot as the arena carves it, each buffer rounded up
+    to 256 bytes: the two input images, both census maps, the cost volume,
+    the two disparity maps, and the workspace of the streamlined aggregation
+    (path slices, S_bar only where the fused selection does not apply, D^R
+    keys, D^L)."""
     n = spec.width * spec.height
     nd = spec.ndisp
     slices = npaths * _a256(n * nd) * (1 if p2 <= 255 else 2)
     fused = nd % 16 == 0 and nd <= 256 and p2 <= 255
     work = _a256(slices) + (0 if fused else _a256(2 * n * nd)) + _a256(4 * n) + _a256(2 * n)
-    return 2 * n + 16 * n + n * nd + work + 4 * n
+    return 2 * _a256(n) + 2 * _a256(8 * n) + _a256(n * nd) + 2 * _a256(2 * n) + _a256(work)
 
 
 class Server:
@@ -147,6 +197,18 @@ class Server:
             self.evictions += 1
         return True
 
+    def _evict_one(self, exclude: int) -> bool:
+        idle = sorted(((slot["last"], t, slot) for t, lst in self.slots.items() for slot in lst
+                       if slot["job"] is None and t != exclude), key=lambda v: v[0])
+        if not idle:
+            return False
+        _, t, slot = idle[0]
+        self.slots[t].remove(slot)
+        self.backend.free_slot(slot["handle"])
+        self.used_bytes -= self.sizes[t]
+        self.evictions += 1
+        return True
+
     def _free_slot(self, s: int) -> Optional[dict]:
         self._tick += 1
         for slot in self.slots[s]:
@@ -158,8 +220,14 @@ class Server:
         if self.used_bytes + self.sizes[s] > self.budget:
             if self.slots[s] or not self._evict_for(self.sizes[s]):
                 return None          # only a stream with no slot may evict others
-        slot = {"id": len(self.slots[s]), "handle": self.backend.alloc_slot(s), "job": None,
-                "last": self._tick}
+        handle = self.backend.alloc_slot(s)
+        while handle is None:
+            # the arena has the bytes but not in one piece: release the least
+            # recently used idle slot of another stream and try again
+            if self.slots[s] or not self._evict_one(exclude=s):
+                return None
+            handle = self.backend.alloc_slot(s)
+        slot = {"id": len(self.slots[s]), "handle": handle, "job": None, "last": self._tick}
         self.slots[s].append(slot)
         self.used_bytes += self.sizes[s]
         return slot
@@ -223,13 +291,16 @@ class FakeBackend:
     """Virtual clock; a frame takes N*D / rate seconds, frames overlap
     freely (CPU tests of the scheduling logic)."""
 
-    def __init__(self, specs, mdes_per_s: float = 1e5):
+    def __init__(self, specs, mdes_per_s: float = 1e5, arena_bytes: Optional[int] = None,
+                 npaths: int = 8, p2: int = 120):
         self.specs = specs
         self.rate = mdes_per_s * 1e6
         self.t = 0.0
         self.live = {}
         self.result_of = {}
         self.submitted = []
+        self.arena = Arena(arena_bytes) if arena_bytes else None
+        self.sizes = [slot_bytes(sp, npaths, p2) for sp in specs]
 
     def start(self):
         self.t = 0.0
@@ -238,10 +309,17 @@ class FakeBackend:
         return self.t
 
     def alloc_slot(self, s):
+        off = None
+        if self.arena is not None:
+            off = self.arena.alloc(self.sizes[s])
+            if off is None:
+                return None
         self.allocs = getattr(self, "allocs", 0) + 1
-        return ("slot", s)
+        return ("slot", s, off)
 
     def free_slot(self, handle):
+        if self.arena is not None:
+            self.arena.release(handle[2], self.sizes[handle[1]])
         self.frees = getattr(self, "frees", 0) + 1
 
     def submit(self, s, slot, req, keep):
@@ -266,10 +344,12 @@ class FakeBackend:
 
 
 class GpuBackend:
-    """Slots are StereoSGM buffer sets with their own device inputs; frames
-    run on a pool of HIP streams (default priority)."""
+    """Slots are StereoSGM buffer sets, with their own device inputs, carved
+    out of one device arena; frames run on a pool of HIP streams (default
+    priority)."""
 
-    def __init__(self, specs, params, frames_per_stream: int = 4, device="cuda", occlusion=0.05):
+    def __init__(self, specs, params, frames_per_stream: int = 4, device="cuda", occlusion=0.05,
+                 arena_bytes: int = 8 << 30):
         import torch
 
         from . import sgm
@@ -283,6 +363,12 @@ class GpuBackend:
                 frames.append((torch.from_numpy(pair["left"]).pin_memory(),
                                torch.from_numpy(pair["right"]).pin_memory()))
             self.pool.append(frames)
+        self.sizes = [slot_bytes(sp, params.npaths, params.p2) for sp in specs]
+        self.arena = Arena(arena_bytes)
+        # the one device allocation of the server: every slot lives in it
+        self.memory = torch.empty(self.arena.capacity + Arena.ALIGN, dtype=torch.uint8,
+                                  device=self.device)
+        self.base = (-self.memory.data_ptr()) % Arena.ALIGN
         self.result_of = {}
         self.t0_event = None
         self.t0 = 0.0
@@ -301,12 +387,27 @@ class GpuBackend:
         return time.perf_counter() - self.t0
 
     def alloc_slot(self, s):
+        """A slot's buffers carved from the arena, or None if they do not fit
+        in one free range."""
         torch, sgm = self.torch, self.sgm
         sp = self.specs[s]
+        off = self.arena.alloc(self.sizes[s])
+        if off is None:
+            return None
+        cursor = [self.base + off]
+
+        def take(nbytes):
+            start = cursor[0]
+            cursor[0] += _a256(nbytes)
+            return self.memory[start: start + nbytes]
+
+        n = sp.width * sp.height
         prm = sgm.Params(**{**self.params.__dict__, "ndisp": sp.ndisp})
-        return {"eng": sgm.StereoSGM(sp.width, sp.height, prm, device=self.device),
-                "left": torch.empty((sp.height, sp.width), dtype=torch.uint8, device=self.device),
-                "right": torch.empty((sp.height, sp.width), dtype=torch.uint8, device=self.device),
+        left = take(n).view(sp.height, sp.width)
+        right = take(n).view(sp.height, sp.width)
+        eng = sgm.StereoSGM(sp.width, sp.height, prm, device=self.device, alloc=take)
+        assert cursor[0] - self.base - off <= self.sizes[s], "slot layout exceeds slot_bytes"
+        return {"eng": eng, "left": left, "right": right, "off": off, "stream_index": s,
                 "out": torch.empty((sp.height, sp.width), dtype=torch.uint16).pin_memory(),
                 "stream": torch.cuda.Stream(device=self.device)}
 
@@ -333,7 +434,9 @@ class GpuBackend:
         return self.t0_event.elapsed_time(ev) * 1e-3
 
     def free_slot(self, handle):
-        handle.clear()       # the caching allocator keeps the memory for the next slot
+        # only idle slots are released: their last frame has completed
+        self.arena.release(handle["off"], self.sizes[handle["stream_index"]])
+        handle.clear()
 
     def idle(self, next_arrival=None):
         time.sleep(5e-5)
@@ -345,6 +448,8 @@ class GpuBackend:
 
 
 def serve_plain(trace, specs, backend) -> Stats:
-    """FIFO reference: one frame at a time, in arrival order, one stream."""
-    srv = Server(specs, backend, budget_bytes=1 << 62, hip_streams=1, max_slots_per_stream=1)
+    """FIFO reference: one frame at a time, in arrival order, one stream, one
+    slot per stream (within the backend's arena)."""
+    srv = Server(specs, backend, budget_bytes=backend.arena.capacity if getattr(
+        backend, "arena", None) is not None else 1 << 62, hip_streams=1, max_slots_per_stream=1)
     return srv.run(trace)

@@ -378,23 +378,49 @@ class StereoSGM:
     sgm_cost, sgm_aggregate, sgm_wta_lrc instead (same bits, S_bar kept in
     self.agg)."""
 
-    def __init__(self, width: int, height: int, params: Params, device="cuda", fused: bool = True):
+    def __init__(self, width: int, height: int, params: Params, device="cuda", fused: bool = True,
+                 alloc=None):
+        """alloc(nbytes) -> uint8 device tensor of nbytes, 256-byte aligned:
+        where every buffer comes from (default: a fresh allocation each)."""
         self.width, self.height, self.params, self.fused = width, height, params, fused
         dev = torch.device(device)
         nd = params.ndisp
-        self.census_left = _empty((height, width), torch.uint64, dev)
-        self.census_right = _empty((height, width), torch.uint64, dev)
-        self.cost = _empty((height, width, nd), torch.uint8, dev)
-        self.disp = _empty((height, width), torch.uint16, dev)
-        self.disp_right = _empty((height, width), torch.uint16, dev)
+        if alloc is None:
+            def alloc(nbytes):
+                return _aligned_bytes(nbytes, dev)
+
+        def buf(shape, dtype):
+            n = 1
+            for s in shape:
+                n *= s
+            item = torch.empty((), dtype=dtype).element_size()
+            return alloc(max(1, n) * item)[: n * item].view(dtype).view(shape)
+
+        self.census_left = buf((height, width), torch.uint64)
+        self.census_right = buf((height, width), torch.uint64)
+        self.cost = buf((height, width, nd), torch.uint8)
+        self.disp = buf((height, width), torch.uint16)
+        self.disp_right = buf((height, width), torch.uint16)
         if fused:
-            self.select_work = _aligned_bytes(
-                max(1, aggregate_select_work_bytes(width, height, nd, params.npaths, params.p2)), dev)
+            self.select_work = alloc(max(1, aggregate_select_work_bytes(width, height, nd,
+                                                                        params.npaths, params.p2)))
         else:
-            self.agg = _empty((height, width, nd), torch.uint16, dev)
-            self.agg_work = _empty((max(1, aggregate_work_bytes(width, height, nd, params.npaths,
-                                                                params.p2)),), torch.uint8, dev)
-            self.work = _empty((wta_lrc_work_elems(width, height),), torch.uint16, dev)
+            self.agg = buf((height, width, nd), torch.uint16)
+            self.agg_work = alloc(max(1, aggregate_work_bytes(width, height, nd, params.npaths,
+                                                              params.p2)))
+            self.work = buf((wta_lrc_work_elems(width, height),), torch.uint16)
+
+    @staticmethod
+    def buffer_bytes(width: int, height: int, params: Params, fused: bool = True) -> list:
+        """Sizes of the device buffers __init__ asks `alloc` for, in order."""
+        n, nd = width * height, params.ndisp
+        sizes = [8 * n, 8 * n, n * nd, 2 * n, 2 * n]
+        if fused:
+            sizes.append(aggregate_select_work_bytes(width, height, nd, params.npaths, params.p2))
+        else:
+            sizes += [2 * n * nd, aggregate_work_bytes(width, height, nd, params.npaths, params.p2),
+                      2 * wta_lrc_work_elems(width, height)]
+        return [max(1, b) for b in sizes]
 
     def run(self, left: torch.Tensor, right: torch.Tensor, stream=None) -> torch.Tensor:
         p = self.params

@@ -3,6 +3,7 @@ bit-identical to its plain per-frame result through the four ABI calls and
 to the oracle; graph replays with eager work and input changes in between
 stay exact; every path-kernel lane-layout variant gives identical bits."""
 import json
+import os
 import sys
 
 import numpy as np
@@ -10,6 +11,9 @@ import pytest
 
 import oracle
 from paper_2106_07927_amd import datagen
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import oracle_digests as od  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -141,9 +145,13 @@ def test_batch_4path_5x5_and_u16_slices(torch_dev):
         plan.close()
 
 
-def test_batch_mixed_workload_matches_plain(torch_dev):
+def test_batch_mixed_workload_matches_plain_and_oracle(torch_dev):
     """The 64-pair mixed batch (sizes from 320x240 to 1920x1080, D from 64
-    to 256): each pair bit-identical to its plain per-frame result."""
+    to 256): each pair bit-identical to its plain per-frame result, and the
+    first pair of every distinct (W, H, D) -- all twelve, including the
+    frames of 100k pixels and more that run the single-frame kernels inside
+    the graph -- equal to the oracle in D and D^R (stored oracle digests,
+    tests/golden/oracle_digests.json)."""
     torch, dev = torch_dev
     from paper_2106_07927_amd import sgm
     say("64-pair mixed batch")
@@ -154,9 +162,24 @@ def test_batch_mixed_workload_matches_plain(torch_dev):
         a, b = datagen.random_images(w, h, seed=seed)
         lefts.append(torch.from_numpy(a).to(dev))
         rights.append(torch.from_numpy(b).to(dev))
-    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in specs], prm)
+    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in specs], prm, want_right=True)
     plan.run()
     torch.cuda.synchronize()
+    table = od.load()["cases"]
+    checked = set()
+    for i, (w, h, nd, seed) in enumerate(specs):
+        if (w, h, nd) in checked:
+            continue
+        checked.add((w, h, nd))
+        case = table[f"batch_{w}x{h}x{nd}"]
+        assert case["spec"]["seed"] == seed, "batch mix changed: rerun tests/golden/oracle_digests.py"
+        assert od.digest(lefts[i].cpu().numpy()) == case["inputs"]["left"]
+        assert od.digest(rights[i].cpu().numpy()) == case["inputs"]["right"]
+        assert od.digest(plan.disp[i].cpu().numpy()) == case["outputs"]["disp"], \
+            f"pair {i} {(w, h, nd)}: D differs from the oracle"
+        assert od.digest(plan.disp_right[i].cpu().numpy()) == case["outputs"]["disp_right"], \
+            f"pair {i} {(w, h, nd)}: D^R differs from the oracle"
+    assert len(checked) == 12
     engines = {}
     for i, (w, h, nd, _) in enumerate(specs):
         key = (w, h, nd)

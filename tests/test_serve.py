@@ -1,7 +1,9 @@
 """Serving scheduler on the CPU (virtual clock, simulated service times):
 every request is served once, per-stream FIFO admission, the HBM budget is
 never exceeded, small budgets defer and evict instead of deadlocking,
-oversized streams are rejected, and the plain reference never overlaps."""
+oversized streams are rejected, and the plain reference never overlaps.
+The slot arena: first-fit placement, coalescing on release, and a scheduler
+that evicts further when the free bytes are there but not in one piece."""
 import numpy as np
 
 from paper_2106_07927_amd import serve
@@ -83,9 +85,44 @@ def test_slot_bytes_match_the_library_workspace():
         import pytest
         pytest.skip("libsgm.so not built")
     lib = sgm.load_library()
+    a = serve.Arena.round
     for sp in specs() + [StreamSpec(320, 240, 100, 5), StreamSpec(64, 48, 7, 6)]:
-        for p2 in (120, 300):
-            n = sp.width * sp.height
-            fixed = 2 * n + 16 * n + n * sp.ndisp + 4 * n
-            work = lib.sgm_aggregate_select_work_bytes(sp.width, sp.height, sp.ndisp, 8, p2)
-            assert serve.slot_bytes(sp, 8, p2) == fixed + work
+        for npaths in (4, 8):
+            for p2 in (86, 120, 127, 128, 200, 300):
+                n = sp.width * sp.height
+                fixed = 2 * a(n) + 2 * a(8 * n) + a(n * sp.ndisp) + 2 * a(2 * n)
+                work = lib.sgm_aggregate_select_work_bytes(sp.width, sp.height, sp.ndisp, npaths, p2)
+                assert serve.slot_bytes(sp, npaths, p2) == fixed + a(work), (sp, npaths, p2)
+
+
+def test_arena_first_fit_and_coalescing():
+    ar = serve.Arena(10 * 256 + 17)
+    assert ar.capacity == 10 * 256
+    a = ar.alloc(300)            # 2 units
+    b = ar.alloc(256)            # 1 unit
+    c = ar.alloc(1000)           # 4 units
+    assert (a, b, c) == (0, 512, 768)
+    assert ar.alloc(4 * 256) is None          # 3 units left
+    ar.release(b, 256)
+    assert ar.largest_free() == 3 * 256
+    ar.release(a, 300)                        # merges with b's range
+    assert ar.free[0] == (0, 3 * 256)
+    ar.release(c, 1000)                       # everything merges back
+    assert ar.free == [(0, 10 * 256)] and ar.used == 0
+
+
+def test_arena_fragmentation_forces_extra_evictions():
+    """Budget bytes that are free but split: the scheduler releases more
+    idle slots until one range fits, and never exceeds the arena."""
+    sp = specs()
+    sizes = [serve.slot_bytes(s, 8, 120) for s in sp]
+    budget = serve.Arena.round(max(sizes) + min(sizes) + 2 * sorted(sizes)[1])
+    trace = serve.make_trace(sp, 30.0, 2.0, 4, seed=21)
+    be = FakeBackend(sp, mdes_per_s=2e4, arena_bytes=budget)
+    srv = Server(sp, be, budget_bytes=budget, hip_streams=8)
+    st = srv.run(trace)
+    assert st.served == len(trace) and st.rejected == 0
+    assert st.evictions > 0 and st.deferred > 0
+    assert be.arena.used == sum(serve.Arena.round(srv.sizes[t]) for t, lst in srv.slots.items()
+                                for _ in lst)
+    assert be.arena.used <= be.arena.capacity
