@@ -6,18 +6,24 @@
 One step = one pass of the whole path over one synthetic stereo pair whose
 images are already resident in HBM: census (left and right), Hamming cost,
 8-path aggregation, WTA + approximate D^R + LR check + 3x3 median.  The
-default workload is a 1242x375 pair, D = 128, census 9x7, P1 = 10, P2 = 120.
-The timed path is the streamlined one (aggregation fused with the selection,
-sgm_aggregate_select); the four-call path (sgm_aggregate + sgm_wta_lrc, same
-bits) is timed the same way and reported beside it.  The reported step is the
-fastest of three launch modes, all listed: eager launches on one stream, a
-hipGraph replay, and frames in flight (consecutive steps round-robin over 2-8
-engines with their own buffers and streams; per-step time = wall time / K).
+headline workload is a 1242x375 pair, D = 128, census 9x7, P1 = 10,
+P2 = 120.  The timed path is the streamlined one (aggregation fused with the
+selection, sgm_aggregate_select).
 
-Prints ONE JSON line with the throughput in MDE/s (W * H * D / step time, the
-paper's Eq. mdes), FPS, the dominant unit's roofline fraction (timed with HIP
-events on the stream it runs on), the batched and served forms, and the CPU
-oracle timed on a bounded sample of the same workload.
+Launch mode: eager launches on one stream, a hipGraph replay, and frames in
+flight (consecutive steps round-robin over 2 or 4 engines with their own
+buffers and streams) are each timed over a long untimed sample; the fastest
+is then timed over exactly K steps for the headline, and the eager
+single-stream figure is reported beside it.
+
+Prints ONE JSON line: throughput in MDE/s (W * H * D / step time, the
+paper's Eq. mdes) and FPS; the roofline of the dominant unit
+(sgm_aggregate_select, timed with HIP events on its launch stream) on the
+aggregation's algorithmic bytes (R + 2) N D; the 320x240 and 1920x1080
+workloads; the four-call form and the other forms; the batched form (64
+mixed pairs, one hipGraph) against plain per-frame launches; the served form
+(16 Poisson camera streams, continuous batching against plain FIFO); and the
+CPU oracle timed on the host cores (one thread and all of them).
 """
 from __future__ import annotations
 
@@ -33,6 +39,7 @@ if ROOT not in sys.path:
 
 METRIC = "MDE/s and FPS at 1242x375 D=128 8-path; batched vs plain; p99 latency"
 HBM_PEAK_GBS = 8000.0
+HEADLINE = "c2_1242x375_d128_r8"
 
 
 def parse():
@@ -40,34 +47,40 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2_1242x375_d128_r8")
+    ap.add_argument("--workload", default=HEADLINE)
+    ap.add_argument("--select-steps", type=int, default=200,
+                    help="untimed steps per launch mode when choosing the headline's mode")
     ap.add_argument("--cpu-frames", type=int, default=3,
-                    help="frames of the CPU-oracle sample (0 skips it)")
+                    help="frames of the single-threaded CPU-oracle sample (0 skips the CPU legs)")
     ap.add_argument("--batch-reps", type=int, default=5,
                     help="timed replays of the 64-pair batch (0 skips the batched form)")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served trace (0 skips the served form)")
+    ap.add_argument("--serve-short-seconds", type=float, default=15.0,
+                    help="length of the tight-budget and overload traces")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
-    ap.add_argument("--max-streams", type=int, default=8,
+    ap.add_argument("--max-streams", type=int, default=4,
                     help="largest frames-in-flight count timed (1: single-stream modes only, "
                          "so that a kernel trace sees no overlapping frames)")
+    ap.add_argument("--other-configs", type=int, default=1,
+                    help="time the 320x240 and 1920x1080 workloads too (0 skips them)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the path, run a plain device copy of this many MiB five "
                          "times (the known-size kernel that scales HBM counter readings)")
     return ap.parse_args()
 
 
-# HBM bytes per call at the 1242x375 / D=128 / 8-path frame, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs of this script (profiles/hbm_traffic_1242x375_d128_r8.md), each
-# scaled by what the same counter reads for a plain copy of known size.  An
-# entry holds only for the kernel sources whose digest it names; for any other
-# sources the figure is reported as null.
-TRAFFIC = {
-    "sgm_aggregate_select": {"sources": "1436e5dd61f586fc", "bytes": 1485239781},
-    "sgm_aggregate": {"sources": "1436e5dd61f586fc", "bytes": 1587875114},
+# Counter readings for the dominant unit at the 1242x375 / D=128 / 8-path
+# frame (profiles/), per call: HBM bytes from FETCH_SIZE and WRITE_SIZE, each
+# scaled by its reading for a plain copy of known size, and the VALU-busy
+# share of the path kernel from SQ_INSTS_VALU.  An entry holds only for the
+# kernel sources whose digest it names; otherwise the figures are null.
+COUNTERS = {
+    "sgm_aggregate_select": {"sources": None, "traffic": None, "valu_busy": None},
 }
 
-KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "wta_lrc.hip", "sgm_internal.h")
+KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "paths.hip", "wta_lrc.hip",
+                  "sgm_internal.h")
 
 
 def sources_digest():
@@ -79,11 +92,16 @@ def sources_digest():
     return hsh.hexdigest()[:16]
 
 
-def traffic(unit, digest):
-    entry = TRAFFIC.get(unit)
+def counters(unit, digest):
+    entry = COUNTERS.get(unit)
     if entry is None or entry["sources"] != digest:
-        return None
-    return entry["bytes"]
+        return None, None
+    return entry["traffic"], entry["valu_busy"]
+
+
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def percentile(sorted_vals, q):
@@ -102,101 +120,217 @@ def copy_probe(torch, dev, mib):
     del src, dst
 
 
-def batched_form(args, torch, dev, sgm, datagen):
-    """64 mixed pairs: one hipGraph replay per batch vs 64 plain per-frame
-    pipelines on one stream."""
-    from paper_2106_07927_amd import tune
-    specs = datagen.batch_specs()
-    base = datagen.CONFIGS["c2_1242x375_d128_r8"]
-    params = sgm.Params(ndisp=0, win_w=base["win_w"], win_h=base["win_h"], npaths=base["npaths"],
-                        p1=base["p1"], p2=base["p2"], lr_tolerance=base["lr_tolerance"],
-                        median3x3=base["median3x3"])
-    lefts, rights = [], []
-    for (w, h, nd, seed) in specs:
-        pair = datagen.make_pair(w, h, nd, seed, base["planes"], base["occlusion"])
-        lefts.append(torch.from_numpy(pair["left"]).to(dev))
-        rights.append(torch.from_numpy(pair["right"]).to(dev))
-    table, tune_ms = tune.tune([(w, h, nd) for (w, h, nd, _) in specs], params, device=dev)
-    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in specs], params, tune_table=json.dumps(table))
-    plan.run()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.batch_reps):
-        plan.run()
-    t1.record()
-    torch.cuda.synchronize()
-    batch_ms = t0.elapsed_time(t1) / args.batch_reps
-    plan.close()
-    del plan
-    engines = {}
-    for (w, h, nd, _) in specs:
-        if (w, h, nd) not in engines:
-            engines[(w, h, nd)] = sgm.StereoSGM(w, h, sgm.Params(**{**params.__dict__, "ndisp": nd}), device=dev)
+def params_of(sgm, cfg):
+    return sgm.Params(win_w=cfg["win_w"], win_h=cfg["win_h"], ndisp=cfg["ndisp"],
+                      npaths=cfg["npaths"], p1=cfg["p1"], p2=cfg["p2"],
+                      lr_tolerance=cfg["lr_tolerance"], median3x3=cfg["median3x3"])
 
-    def plain():
-        for i, (w, h, nd, _) in enumerate(specs):
-            engines[(w, h, nd)].run(lefts[i], rights[i])
 
-    plain()
+def workload_desc(name, cfg):
+    return (f"{name}: {cfg['width']}x{cfg['height']} uint8 pair, D={cfg['ndisp']}, census "
+            f"{cfg['win_w']}x{cfg['win_h']}, {cfg['npaths']} paths, P1={cfg['p1']}, P2={cfg['p2']}, "
+            f"LR tol {cfg['lr_tolerance']}, median {int(cfg['median3x3'])}")
+
+
+class Frame:
+    """One workload's pair on the device and the calls of one step."""
+
+    def __init__(self, torch, sgm, datagen, name, dev):
+        self.torch, self.sgm = torch, sgm
+        self.name = name
+        self.cfg = cfg = datagen.CONFIGS[name]
+        self.w, self.h, self.nd, self.npaths = cfg["width"], cfg["height"], cfg["ndisp"], cfg["npaths"]
+        self.prm = params_of(sgm, cfg)
+        self.pair = datagen.config_pair(name)
+        self.left = torch.from_numpy(self.pair["left"]).to(dev)
+        self.right = torch.from_numpy(self.pair["right"]).to(dev)
+        self.dev = dev
+        self.des = self.w * self.h * self.nd
+
+    def engine(self, fused=True):
+        return self.sgm.StereoSGM(self.w, self.h, self.prm, device=self.dev, fused=fused)
+
+    def step(self, eng, stream, ev=None, fused=True):
+        """The whole path once; with `ev`, events at the stage boundaries."""
+        sgm, prm = self.sgm, self.prm
+
+        def mark(i):
+            if ev is not None:
+                ev[i].record(stream)
+        mark(0)
+        if fused:
+            sgm.sgm_census_pair(self.left, self.right, prm.win_w, prm.win_h, out_left=eng.census_left,
+                                out_right=eng.census_right, stream=stream)
+        else:
+            sgm.sgm_census(self.left, prm.win_w, prm.win_h, out=eng.census_left, stream=stream)
+            sgm.sgm_census(self.right, prm.win_w, prm.win_h, out=eng.census_right, stream=stream)
+        mark(1)
+        sgm.sgm_cost(eng.census_left, eng.census_right, self.nd, out=eng.cost, stream=stream)
+        mark(2)
+        if fused:
+            sgm.sgm_aggregate_select(eng.cost, self.npaths, prm.p1, prm.p2, prm.lr_tolerance,
+                                     prm.median3x3, out=eng.disp, out_right=eng.disp_right,
+                                     work=eng.select_work, stream=stream)
+            mark(3)
+        else:
+            sgm.sgm_aggregate(eng.cost, self.npaths, prm.p1, prm.p2, out=eng.agg, work=eng.agg_work,
+                              stream=stream)
+            mark(3)
+            sgm.sgm_wta_lrc(eng.agg, prm.lr_tolerance, prm.median3x3, out=eng.disp,
+                            out_right=eng.disp_right, work=eng.work, stream=stream)
+            mark(4)
+
+    def stage_times(self, eng, stream, steps, fused=True):
+        """Per-stage average ms and sorted per-step ms over `steps` eager steps,
+        from events on the launch stream."""
+        torch = self.torch
+        names = ("census", "cost", "aggregate_select") if fused else \
+            ("census", "cost", "aggregate", "wta_lrc")
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+               for _ in range(steps)]
+        torch.cuda.synchronize()
+        for i in range(steps):
+            self.step(eng, stream, evs[i], fused)
+        torch.cuda.synchronize()
+        per_step = sorted(e[0].elapsed_time(e[-1]) for e in evs)
+        stages = {nm: sum(e[a].elapsed_time(e[a + 1]) for e in evs) / steps
+                  for a, nm in enumerate(names)}
+        return stages, per_step
+
+    def roofline(self, agg_ms, digest=None):
+        """The aggregation's algorithmic bytes (R + 2) N D -- R reads of the
+        uint8 cost volume and one uint16 write of S_bar -- over the duration of
+        the sgm_aggregate_select call (paths, fused selection, check/median)."""
+        b = (self.npaths + 2) * self.des
+        achieved = b / (agg_ms * 1e-3) / 1e9
+        traffic, valu = counters("sgm_aggregate_select", digest) if digest else (None, None)
+        second = self.npaths * self.des + 4 * self.w * self.h
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "sgm_aggregate_select (paths_kernel + select_fused_kernel + "
+                          "check_median_kernel)",
+                "algorithmic_bytes": b, "t_agg_us": round(agg_ms * 1e3, 2),
+                "basis": "(R+2)*N*D: the cost volume streamed once per path plus S_bar written "
+                         "once, over the whole aggregate_select call",
+                "valu_busy": valu,
+                "frac_on_read_bytes": round(second / (agg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def headline(args, torch, sgm, datagen, dev):
+    fr = Frame(torch, sgm, datagen, args.workload, dev)
+    stream = torch.cuda.current_stream()
+    eng = fr.engine()
+    for _ in range(args.warmup):
+        fr.step(eng, stream)
     torch.cuda.synchronize()
-    t0.record()
-    reps = max(1, args.batch_reps // 2)
-    for _ in range(reps):
-        plain()
-    t1.record()
+
+    def run_eager(n):
+        for _ in range(n):
+            fr.step(eng, stream)
+
+    graph = eng.capture(fr.left, fr.right)
+
+    def run_graph(n):
+        for _ in range(n):
+            graph.replay()
+
+    def make_streams(k):
+        engs = [fr.engine() for _ in range(k)]
+        side = [torch.cuda.Stream(device=dev) for _ in range(k)]
+
+        def run(n):
+            for i in range(n):
+                engs[i % k].run(fr.left, fr.right, stream=side[i % k])
+        return run, engs
+
+    modes = {"eager": run_eager, "hipgraph": run_graph}
+    stream_engines = []
+    for k in (2, 4):
+        if k <= args.max_streams:
+            run, engs = make_streams(k)
+            modes[f"streams{k}"] = run
+            stream_engines += engs
+
+    def wall_ms(run, n):
+        run(max(2, args.warmup // 2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(n)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    # choose the launch mode on long untimed samples
+    mode_ms = {m: wall_ms(run, args.select_steps) for m, run in modes.items()}
+    mode = min(mode_ms, key=mode_ms.get)
+    # the headline: exactly K steps in that mode, synchronised on both sides
+    run = modes[mode]
+    run(args.warmup)
     torch.cuda.synchronize()
-    plain_ms = t0.elapsed_time(t1) / reps
-    des = sum(w * h * nd for (w, h, nd, _) in specs)
-    del engines
+    t0 = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    for e in stream_engines:
+        if not (torch.equal(e.disp, eng.disp) and torch.equal(e.disp_right, eng.disp_right)):
+            raise RuntimeError("a frames-in-flight result differs from the single-stream one")
+    # eager single stream with stage events: the dominant unit's duration
+    stages, per_step = fr.stage_times(eng, stream, max(args.steps, 20))
+    return fr, eng, {"mode": mode, "ms": ms, "mode_ms": mode_ms, "stages": stages,
+                     "per_step": per_step}
+
+
+def other_config(args, torch, sgm, datagen, dev, name, digest):
+    fr = Frame(torch, sgm, datagen, name, dev)
+    stream = torch.cuda.current_stream()
+    eng = fr.engine()
+    steps = max(20, min(args.steps, 200 if fr.des < 10 ** 8 else 30))
+    for _ in range(3):
+        fr.step(eng, stream)
+    stages, per_step = fr.stage_times(eng, stream, steps)
+    ms = sum(stages.values())
+    out = {"workload": workload_desc(name, fr.cfg), "steps": steps, "ms_per_step": round(ms, 5),
+           "value": round(fr.des / (ms * 1e-3) / 1e6, 1), "unit": "MDE/s",
+           "fps": round(1000.0 / ms, 1), "launch": "eager",
+           "stages_ms": {k: round(v, 5) for k, v in stages.items()},
+           "step_ms_p50": round(percentile(per_step, 0.5), 5),
+           "step_ms_p99": round(percentile(per_step, 0.99), 5),
+           "roofline": fr.roofline(stages["aggregate_select"])}
+    del eng
     torch.cuda.empty_cache()
-    return {"pairs": len(specs), "des_per_batch": des,
-            "ms_per_batch": round(batch_ms, 3), "mdes": round(des / batch_ms / 1e3, 1),
-            "fps": round(len(specs) / batch_ms * 1e3, 1),
-            "plain_ms_per_batch": round(plain_ms, 3), "plain_mdes": round(des / plain_ms / 1e3, 1),
-            "speedup": round(plain_ms / batch_ms, 3), "tune_table": table, "tune_ms": tune_ms,
-            "launch": "one hipGraph replay (persistent work-list kernels per stage)"}
+    return out
 
 
-def served_form(args, torch, sgm, datagen):
-    """16 Poisson camera streams at 30 Hz: continuous batching vs plain FIFO."""
-    from paper_2106_07927_amd import serve
-    base = datagen.CONFIGS["c2_1242x375_d128_r8"]
-    params = sgm.Params(ndisp=0, win_w=base["win_w"], win_h=base["win_h"], npaths=base["npaths"],
-                        p1=base["p1"], p2=base["p2"], lr_tolerance=base["lr_tolerance"],
-                        median3x3=base["median3x3"])
-    specs = [serve.StreamSpec(*s) for s in datagen.stream_specs()]
-    backend = serve.GpuBackend(specs, params, frames_per_stream=2)
-    trace = serve.make_trace(specs, 30.0, args.serve_seconds, 2, seed=2110)
-    budget = int(args.serve_budget_gib * 2 ** 30)
-    # warm-up over the trace's first second (not reported): the first slots'
-    # device allocations would otherwise land in the measured latencies
-    serve.Server(specs, backend, budget_bytes=budget, hip_streams=4).run(
-        [r for r in trace if r.arrival < 1.0])
-    torch.cuda.synchronize()
-    mix = serve.Server(specs, backend, budget_bytes=budget, hip_streams=4).run(trace)
-    torch.cuda.synchronize()
-    tight = serve.Server(specs, backend, budget_bytes=8 * 2 ** 30, hip_streams=4).run(trace)
-    torch.cuda.synchronize()
-    fifo = serve.serve_plain(trace, specs, backend)
-    torch.cuda.synchronize()
-    offered = sum(s.width * s.height * s.ndisp for s in specs) * 30.0 / 1e6
-    return {"streams": len(specs), "rate_hz": 30.0, "seconds": args.serve_seconds,
-            "offered_mdes": round(offered, 1), "budget_gib": args.serve_budget_gib,
-            "continuous": mix.summary(specs), "tight_budget_8gib": tight.summary(specs),
-            "plain_fifo": fifo.summary(specs)}
+def four_call(args, torch, fr):
+    stream = torch.cuda.current_stream()
+    eng = fr.engine(fused=False)
+    for _ in range(args.warmup):
+        fr.step(eng, stream, fused=False)
+    stages, per_step = fr.stage_times(eng, stream, max(args.steps, 20), fused=False)
+    ms = sum(stages.values())
+    agg_bytes = (fr.npaths + 2) * fr.des
+    ach = agg_bytes / (stages["aggregate"] * 1e-3) / 1e9
+    del eng
+    return {"ms_per_step": round(ms, 5), "value": round(fr.des / (ms * 1e-3) / 1e6, 1),
+            "stages_ms": {k: round(v, 5) for k, v in stages.items()},
+            "step_ms_p50": round(percentile(per_step, 0.5), 5),
+            "step_ms_p99": round(percentile(per_step, 0.99), 5),
+            "roofline_sgm_aggregate": {
+                "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "sgm_aggregate (paths_kernel + merge_kernel)",
+                "algorithmic_bytes": agg_bytes}}
 
 
-def other_forms(args, torch, sgm, eng, left, right, prm, stream, des):
-    """The same frame through the subpixel form (the paper's "fine") and the
-    exact consistency check ("exact-cc"), timed like the main path."""
+def other_forms(args, torch, sgm, fr, eng):
+    """The same frame through the subpixel form (the paper's "fine"), the
+    exact consistency check ("exact-cc") and the NCC cost, timed like the
+    main path."""
+    left, right, prm, stream, des = fr.left, fr.right, fr.prm, torch.cuda.current_stream(), fr.des
     reps = max(1, min(50, args.steps))
     fine_work = sgm._aligned_bytes(sgm.aggregate_select_subpixel_work_bytes(
-        eng.width, eng.height, prm.ndisp, prm.npaths, prm.p2), left.device)
-    fine_out = torch.empty((eng.height, eng.width), dtype=torch.float32, device=left.device)
-    exact_work = sgm._aligned_bytes(sgm.disparity_exact_lr_work_bytes(eng.width, eng.height, prm),
-                                    left.device)
+        fr.w, fr.h, prm.ndisp, prm.npaths, prm.p2), left.device)
+    fine_out = torch.empty((fr.h, fr.w), dtype=torch.float32, device=left.device)
+    exact_work = sgm._aligned_bytes(sgm.disparity_exact_lr_work_bytes(fr.w, fr.h, prm), left.device)
 
     def fine():
         sgm.sgm_census_pair(left, right, prm.win_w, prm.win_h, out_left=eng.census_left,
@@ -208,10 +342,10 @@ def other_forms(args, torch, sgm, eng, left, right, prm, stream, des):
     def exact():
         sgm.sgm_disparity_exact_lr(left, right, prm, out=eng.disp, work=exact_work)
 
-    # NCC cost (the paper's KITTI penalties for it: P1 = 90, P2 = 880, which
-    # take the uint16 path slices and the unfused selection)
+    # NCC cost with the paper's KITTI penalties for it (P1 = 90, P2 = 880:
+    # uint16 pair slices, still the fused selection)
     ncc_work = sgm._aligned_bytes(sgm.aggregate_select_work_bytes(
-        eng.width, eng.height, prm.ndisp, prm.npaths, 880), left.device)
+        fr.w, fr.h, prm.ndisp, prm.npaths, 880), left.device)
 
     def ncc(win):
         def run():
@@ -243,19 +377,211 @@ def other_forms(args, torch, sgm, eng, left, right, prm, stream, des):
     return out
 
 
-def cpu_baseline(pair, cfg, frames):
+def pcie_frame(args, torch, fr, eng):
+    """PCIe-inclusive frame (context only): pinned H2D of the pair, the path,
+    D2H of D."""
+    stream = torch.cuda.current_stream()
+    hl = torch.from_numpy(fr.pair["left"]).pin_memory()
+    hr = torch.from_numpy(fr.pair["right"]).pin_memory()
+    hd = torch.empty((fr.h, fr.w), dtype=torch.uint16).pin_memory()
+    n = max(1, min(50, args.steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        fr.left.copy_(hl, non_blocking=True)
+        fr.right.copy_(hr, non_blocking=True)
+        fr.step(eng, stream)
+        hd.copy_(eng.disp, non_blocking=True)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / n
+
+
+def batched_form(args, torch, dev, sgm, datagen):
+    """64 mixed pairs: one hipGraph replay per batch vs 64 plain per-frame
+    pipelines on one stream."""
+    from paper_2106_07927_amd import tune
+    specs = datagen.batch_specs()
+    base = datagen.CONFIGS[HEADLINE]
+    params = params_of(sgm, {**base, "ndisp": 0})
+    lefts, rights = [], []
+    for (w, h, nd, seed) in specs:
+        pair = datagen.make_pair(w, h, nd, seed, base["planes"], base["occlusion"])
+        lefts.append(torch.from_numpy(pair["left"]).to(dev))
+        rights.append(torch.from_numpy(pair["right"]).to(dev))
+    table, tune_ms = tune.tune([(w, h, nd) for (w, h, nd, _) in specs], params, device=dev)
+    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in specs], params, tune_table=json.dumps(table))
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.batch_reps):
+        plan.run()
+    t1.record()
+    torch.cuda.synchronize()
+    batch_ms = t0.elapsed_time(t1) / args.batch_reps
+    plan.close()
+    del plan
+    engines = {}
+    for (w, h, nd, _) in specs:
+        if (w, h, nd) not in engines:
+            engines[(w, h, nd)] = sgm.StereoSGM(w, h, sgm.Params(**{**params.__dict__, "ndisp": nd}),
+                                                device=dev)
+
+    def plain():
+        for i, (w, h, nd, _) in enumerate(specs):
+            engines[(w, h, nd)].run(lefts[i], rights[i])
+
+    plain()
+    torch.cuda.synchronize()
+    t0.record()
+    reps = max(1, args.batch_reps // 2)
+    for _ in range(reps):
+        plain()
+    t1.record()
+    torch.cuda.synchronize()
+    plain_ms = t0.elapsed_time(t1) / reps
+    des = sum(w * h * nd for (w, h, nd, _) in specs)
+    del engines
+    torch.cuda.empty_cache()
+    return {"pairs": len(specs), "des_per_batch": des,
+            "ms_per_batch": round(batch_ms, 3), "mdes": round(des / batch_ms / 1e3, 1),
+            "fps": round(len(specs) / batch_ms * 1e3, 1),
+            "plain_ms_per_batch": round(plain_ms, 3), "plain_mdes": round(des / plain_ms / 1e3, 1),
+            "speedup": round(plain_ms / batch_ms, 3), "tune_table": table, "tune_ms": tune_ms,
+            "launch": "one hipGraph replay (work-list kernels for the small frames, the "
+                      "single-frame kernels for the others)"}
+
+
+def served_form(args, torch, sgm, datagen):
+    """16 Poisson camera streams at 30 Hz: continuous batching vs plain FIFO
+    on the same trace; a budget below the streams' slots; twice the rate."""
+    from paper_2106_07927_amd import serve
+    params = params_of(sgm, {**datagen.CONFIGS[HEADLINE], "ndisp": 0})
+    specs = [serve.StreamSpec(*s) for s in datagen.stream_specs()]
+    budget = int(args.serve_budget_gib * 2 ** 30)
+    backend = serve.GpuBackend(specs, params, frames_per_stream=2, arena_bytes=budget)
+    # standalone device time of one frame per stream shape: the GPU-busy estimate
+    frame_ms = {}
+    stream = torch.cuda.current_stream()
+    for s, sp in enumerate(specs):
+        key = (sp.width, sp.height, sp.ndisp)
+        if key in frame_ms:
+            continue
+        prm = sgm.Params(**{**params.__dict__, "ndisp": sp.ndisp})
+        eng = sgm.StereoSGM(sp.width, sp.height, prm)
+        hl, hr = backend.pool[s][0]
+        l, r = hl.cuda(), hr.cuda()
+        for _ in range(3):
+            eng.run(l, r)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(10):
+            eng.run(l, r)
+        b.record(stream)
+        torch.cuda.synchronize()
+        frame_ms[key] = a.elapsed_time(b) / 10
+        del eng
+    torch.cuda.empty_cache()
+
+    def busy(stats):
+        span = max((r.done for r in stats.results), default=0.0)
+        dev_s = sum(frame_ms[(specs[r.request.stream].width, specs[r.request.stream].height,
+                              specs[r.request.stream].ndisp)] for r in stats.results) * 1e-3
+        return round(dev_s / span, 3) if span > 0 else None
+
+    def run(trace, hip_streams=4):
+        torch.cuda.synchronize()
+        st = serve.Server(specs, backend, budget_bytes=backend.arena.capacity,
+                          hip_streams=hip_streams).run(trace)
+        torch.cuda.synchronize()
+        return {**st.summary(specs), "gpu_busy": busy(st)}
+
+    def fifo(trace):
+        st = serve.serve_plain(trace, specs, backend)
+        torch.cuda.synchronize()
+        return {**st.summary(specs), "gpu_busy": busy(st)}
+
+    trace = serve.make_trace(specs, 30.0, args.serve_seconds, 2, seed=2110)
+    short = [r for r in trace if r.arrival < args.serve_short_seconds]
+    # warm-up (not reported): the first launches of every shape
+    run([r for r in trace if r.arrival < 1.0])
+    before = torch.cuda.memory_allocated()
+    mix = run(trace)
+    grown = torch.cuda.memory_allocated() - before
+    # the plain FIFO reference and continuous batching on the same prefix
+    prefix = [r for r in trace if r.arrival < args.serve_short_seconds]
+    prefix_mix = run(prefix)
+    plain = fifo(prefix)
+    # a budget below the streams' slots: waits and evictions inside the arena
+    tight_gib = 8.0
+    tight_backend = serve.GpuBackend(specs, params, frames_per_stream=2,
+                                     arena_bytes=int(tight_gib * 2 ** 30))
+    tb = serve.Server(specs, tight_backend, budget_bytes=tight_backend.arena.capacity,
+                      hip_streams=4).run(short)
+    torch.cuda.synchronize()
+    tight = {**tb.summary(specs), "gpu_busy": busy(tb)}
+    del tight_backend
+    torch.cuda.empty_cache()
+    # over-load: twice the rate
+    fast = serve.make_trace(specs, 60.0, args.serve_short_seconds, 2, seed=2111)
+    over_mix = run(fast)
+    over_fifo = fifo(fast)
+    offered = sum(s.width * s.height * s.ndisp for s in specs) * 30.0 / 1e6
+    return {"streams": len(specs), "rate_hz": 30.0, "seconds": args.serve_seconds,
+            "offered_mdes": round(offered, 1), "arena_gib": round(backend.arena.capacity / 2 ** 30, 2),
+            "slot_gib_all_streams": round(sum(serve.slot_bytes(s, params.npaths, params.p2)
+                                              for s in specs) / 2 ** 30, 2),
+            "device_bytes_allocated_while_serving": grown,
+            "continuous": mix,
+            f"first_{args.serve_short_seconds:g}s": {"continuous": prefix_mix, "plain_fifo": plain},
+            f"tight_arena_{int(tight_gib)}gib_{args.serve_short_seconds:g}s": tight,
+            f"overload_60hz_{args.serve_short_seconds:g}s": {"continuous": over_mix,
+                                                            "plain_fifo": over_fifo},
+            "frame_ms_by_shape": {f"{w}x{h}x{d}": round(v, 4) for (w, h, d), v in frame_ms.items()}}
+
+
+def cpu_baseline(fr, frames):
+    """The oracle on the host: single-threaded (the oracle as it stands) on
+    `frames` frames, then its threaded driver on every core the process may
+    use, checked bit for bit against the single-threaded maps."""
+    import numpy as np
     import oracle
+    cfg = fr.cfg
     prm = oracle.Params(win_w=cfg["win_w"], win_h=cfg["win_h"], ndisp=cfg["ndisp"],
                         npaths=cfg["npaths"], p1=cfg["p1"], p2=cfg["p2"],
                         lr_tolerance=cfg["lr_tolerance"], median3x3=cfg["median3x3"])
     t0 = time.perf_counter()
     for _ in range(frames):
-        oracle.run(pair["left"], pair["right"], prm)
+        ref = oracle.run(fr.pair["left"], fr.pair["right"], prm)
     dt = time.perf_counter() - t0
-    des = cfg["width"] * cfg["height"] * cfg["ndisp"] * frames
+    des = fr.des * frames
+    cores = len(os.sched_getaffinity(0))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mt_frames = 3 * frames
+    t1 = time.perf_counter()
+    for _ in range(mt_frames):
+        mt = oracle.run_threaded(fr.pair["left"], fr.pair["right"], prm, cores)
+    dt_mt = time.perf_counter() - t1
+    same = all(np.array_equal(mt[k], ref[k]) for k in ("disp_left", "disp_right", "disp"))
+    if not same:
+        raise RuntimeError("the threaded oracle differs from the single-threaded one")
     return {"value": round(des / dt / 1e6, 3), "unit": "MDE/s", "cores": 1, "kind": "oracle",
-            "sample": f"{frames} full frames of the {cfg['width']}x{cfg['height']} D={cfg['ndisp']} "
-                      f"{cfg['npaths']}-path workload, single-threaded C oracle, {dt:.1f} s"}
+            "sample": f"{frames} full frames of the {fr.w}x{fr.h} D={fr.nd} {fr.npaths}-path "
+                      f"workload, single-threaded C oracle, {dt:.1f} s",
+            "cpu_model": model,
+            "all_cores": {"value": round(fr.des * mt_frames / dt_mt / 1e6, 3), "unit": "MDE/s",
+                          "cores": cores, "kind": "oracle (threaded driver, same functions)",
+                          "sample": f"{mt_frames} frames, {dt_mt:.1f} s; maps bit-identical to "
+                                    f"the single-threaded run"}}
 
 
 def main():
@@ -270,157 +596,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     dev = torch.device("cuda:0")
-    cfg = datagen.CONFIGS[args.workload]
-    w, h, nd, npaths = cfg["width"], cfg["height"], cfg["ndisp"], cfg["npaths"]
-    prm = sgm.Params(win_w=cfg["win_w"], win_h=cfg["win_h"], ndisp=nd, npaths=npaths,
-                     p1=cfg["p1"], p2=cfg["p2"], lr_tolerance=cfg["lr_tolerance"],
-                     median3x3=cfg["median3x3"])
-    pair = datagen.config_pair(args.workload)
-    left = torch.from_numpy(pair["left"]).to(dev)
-    right = torch.from_numpy(pair["right"]).to(dev)
-    stream = torch.cuda.current_stream()
     if args.copy_probe_mib > 0:
         copy_probe(torch, dev, args.copy_probe_mib)
-
-    def timed(fused):
-        """K timed steps of the whole path after W warm-up steps, bracketed
-        by two events on the launch stream; then K more steps with events at
-        every stage boundary for the per-stage times and percentiles."""
-        eng = sgm.StereoSGM(w, h, prm, device=dev, fused=fused)
-        names = ("census", "cost", "aggregate_select") if fused else \
-            ("census", "cost", "aggregate", "wta_lrc")
-
-        def step(ev=None):
-            def mark(i):
-                if ev is not None:
-                    ev[i].record(stream)
-            mark(0)
-            if fused:
-                sgm.sgm_census_pair(left, right, prm.win_w, prm.win_h, out_left=eng.census_left,
-                                    out_right=eng.census_right)
-            else:
-                sgm.sgm_census(left, prm.win_w, prm.win_h, out=eng.census_left)
-                sgm.sgm_census(right, prm.win_w, prm.win_h, out=eng.census_right)
-            mark(1)
-            sgm.sgm_cost(eng.census_left, eng.census_right, nd, out=eng.cost)
-            mark(2)
-            if fused:
-                sgm.sgm_aggregate_select(eng.cost, npaths, prm.p1, prm.p2, prm.lr_tolerance,
-                                         prm.median3x3, out=eng.disp, out_right=eng.disp_right,
-                                         work=eng.select_work)
-            else:
-                sgm.sgm_aggregate(eng.cost, npaths, prm.p1, prm.p2, out=eng.agg, work=eng.agg_work)
-                mark(3)
-                sgm.sgm_wta_lrc(eng.agg, prm.lr_tolerance, prm.median3x3, out=eng.disp,
-                                out_right=eng.disp_right, work=eng.work)
-            mark(len(names))
-
-        for _ in range(args.warmup):
-            step()
-        t_start = torch.cuda.Event(enable_timing=True)
-        t_end = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t_start.record(stream)
-        for _ in range(args.steps):
-            step()
-        t_end.record(stream)
-        torch.cuda.synchronize()
-        # a second pass of K steps with events at every stage boundary, for
-        # the stage breakdown and the per-step percentiles
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-               for _ in range(args.steps)]
-        for i in range(args.steps):
-            step(evs[i])
-        torch.cuda.synchronize()
-        per_step = sorted(e[0].elapsed_time(e[-1]) for e in evs)
-        stages = {nm: sum(e[a].elapsed_time(e[a + 1]) for e in evs) / args.steps
-                  for a, nm in enumerate(names)}
-        return eng, step, {"ms_per_step": t_start.elapsed_time(t_end) / args.steps,
-                           "stages_ms": stages, "per_step": per_step}
-
-    des = w * h * nd
-    four_eng, _, four = timed(False)
-    del four_eng
-    eng, step, main_t = timed(True)
-    ms_eager = main_t["ms_per_step"]
-
-    # the same path replayed from a HIP graph (launch gaps removed); the
-    # faster of the two launch modes is the reported step
-    graph = eng.capture(left, right)
-    for _ in range(args.warmup):
-        graph.replay()
-    g0 = torch.cuda.Event(enable_timing=True)
-    g1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    g0.record(stream)
-    for _ in range(args.steps):
-        graph.replay()
-    g1.record(stream)
-    torch.cuda.synchronize()
-    ms_graph = g0.elapsed_time(g1) / args.steps
-
-    # frames in flight: consecutive steps go round-robin to n engines, each
-    # with its own buffers and stream (default priority), so one frame's
-    # path pass can overlap another's bandwidth-bound selection.  Every step
-    # still computes its whole frame; each engine's last result is checked
-    # against the single-stream one.
-    def timed_streams(n):
-        engs = [sgm.StereoSGM(w, h, prm, device=dev) for _ in range(n)]
-        side = [torch.cuda.Stream(device=dev) for _ in range(n)]
-        for i in range(max(args.warmup, n)):
-            engs[i % n].run(left, right, stream=side[i % n])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            engs[i % n].run(left, right, stream=side[i % n])
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        for e in engs:
-            if not (torch.equal(e.disp, eng.disp) and torch.equal(e.disp_right, eng.disp_right)):
-                raise RuntimeError(f"{n}-stream result differs from the single-stream one")
-        del engs
-        return ms
-
-    ms_streams = {n: timed_streams(n) for n in (2, 3, 4, 6, 8) if n <= args.max_streams}
-    modes = {"eager": ms_eager, "hipGraph replay": ms_graph}
-    modes.update({f"{n} streams": v for n, v in ms_streams.items()})
-    launch_mode = min(modes, key=modes.get)
-    ms_step = modes[launch_mode]
-    mdes = des / (ms_step * 1e-3) / 1e6
-    per_step = main_t["per_step"]
-
-    # roofline of the dominant unit of the timed path: sgm_aggregate_select,
-    # whose algorithmic bytes are the cost volume streamed once per path plus
-    # the two disparity maps written
-    sel_ms = main_t["stages_ms"]["aggregate_select"]
-    sel_bytes = npaths * des + 4 * w * h
-    achieved = sel_bytes / (sel_ms * 1e-3) / 1e9
-    # the four-call form's sgm_aggregate: R reads of the uint8 volume + one
-    # uint16 write of S_bar
-    agg_ms = four["stages_ms"]["aggregate"]
-    agg_bytes = (npaths + 2) * des
-    agg_achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
-
-    # PCIe-inclusive frame (context only): pinned H2D of the pair, path, D2H of D
-    hl = torch.from_numpy(pair["left"]).pin_memory()
-    hr = torch.from_numpy(pair["right"]).pin_memory()
-    hd = torch.empty((h, w), dtype=torch.uint16).pin_memory()
-    e2e_n = max(1, min(50, args.steps))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(e2e_n):
-        left.copy_(hl, non_blocking=True)
-        right.copy_(hr, non_blocking=True)
-        step()
-        hd.copy_(eng.disp, non_blocking=True)
-    torch.cuda.synchronize()
-    e2e_ms = (time.perf_counter() - t0) * 1e3 / e2e_n
     digest = sources_digest()
-    forms = other_forms(args, torch, sgm, eng, left, right, prm, stream, des)
 
+    log(f"headline {args.workload}: launch modes over {args.select_steps} steps each, then {args.steps} timed")
+    fr, eng, main_t = headline(args, torch, sgm, datagen, dev)
+    log(f"headline done: {main_t['ms']:.4f} ms/step ({main_t['mode']})")
+    ms_step = main_t["ms"]
+    stages = main_t["stages"]
+    per_step = main_t["per_step"]
+    eager_ms = sum(stages.values())
     out = {
         "metric": METRIC,
-        "value": round(mdes, 1),
+        "value": round(fr.des / (ms_step * 1e-3) / 1e6, 1),
         "unit": "MDE/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -431,49 +620,44 @@ def main():
         "vs_baseline": None,
         "dtype": "u16",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {w}x{h} uint8 pair, D={nd}, census "
-                               f"{cfg['win_w']}x{cfg['win_h']}, {npaths} paths, P1={cfg['p1']}, "
-                               f"P2={cfg['p2']}, LR tol {cfg['lr_tolerance']}, "
-                               f"median {int(cfg['median3x3'])}",
-                   "width": w, "height": h, "ndisp": nd, "npaths": npaths, "frames_per_step": 1,
-                   "launch": launch_mode},
-        "launch_modes_ms": {"eager": round(ms_eager, 5), "hipgraph": round(ms_graph, 5),
-                            **{f"streams{n}": round(v, 5) for n, v in ms_streams.items()}},
+        "config": {"workload": workload_desc(args.workload, fr.cfg), "width": fr.w, "height": fr.h,
+                   "ndisp": fr.nd, "npaths": fr.npaths, "frames_per_step": 1,
+                   "launch": main_t["mode"]},
         "fps": round(1000.0 / ms_step, 1),
-        "stages_ms": {k: round(v, 5) for k, v in main_t["stages_ms"].items()},
+        "launch_modes_ms": {k: round(v, 5) for k, v in main_t["mode_ms"].items()},
+        "mode_select_steps": args.select_steps,
+        "eager_single_stream": {"ms_per_step": round(eager_ms, 5),
+                                "value": round(fr.des / (eager_ms * 1e-3) / 1e6, 1),
+                                "fps": round(1000.0 / eager_ms, 1)},
+        "stages_ms": {k: round(v, 5) for k, v in stages.items()},
         "step_ms_p50": round(percentile(per_step, 0.5), 5),
         "step_ms_p99": round(percentile(per_step, 0.99), 5),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic("sgm_aggregate_select", digest),
-                     "kernel": "sgm_aggregate_select (paths_kernel + select_fused_kernel + "
-                               "check_median_kernel)",
-                     "algorithmic_bytes": sel_bytes},
-        "four_call": {"ms_per_step": round(four["ms_per_step"], 5),
-                      "value": round(des / (four["ms_per_step"] * 1e-3) / 1e6, 1),
-                      "stages_ms": {k: round(v, 5) for k, v in four["stages_ms"].items()},
-                      "step_ms_p50": round(percentile(four["per_step"], 0.5), 5),
-                      "step_ms_p99": round(percentile(four["per_step"], 0.99), 5),
-                      "roofline_sgm_aggregate": {
-                          "bound": "hbm", "achieved": round(agg_achieved, 1), "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": round(agg_achieved / HBM_PEAK_GBS, 4),
-                          "traffic": traffic("sgm_aggregate", digest),
-                          "kernel": "sgm_aggregate (paths_kernel + merge_kernel)",
-                          "algorithmic_bytes": agg_bytes}},
-        "e2e_pcie_ms_per_frame": round(e2e_ms, 4),
-        "other_forms": forms,
-        "paper_context": {"value": 644.9, "unit": "MDE/s",
-                          "hardware": "Jetson AGX Xavier, 512-core Volta GPU",
-                          "config": "CT9x7, 8-path SGM, LR check + median, incl. transfers"},
+        "roofline": fr.roofline(stages["aggregate_select"], digest),
     }
+    log("four-call form")
+    out["four_call"] = four_call(args, torch, fr)
+    log("PCIe-inclusive frame and the other forms")
+    out["e2e_pcie_ms_per_frame"] = round(pcie_frame(args, torch, fr, eng), 4)
+    out["other_forms"] = other_forms(args, torch, sgm, fr, eng)
+    out["paper_context"] = {"value": 644.9, "unit": "MDE/s",
+                            "hardware": "Jetson AGX Xavier, 512-core Volta GPU",
+                            "config": "CT9x7, 8-path SGM, LR check + median, incl. transfers"}
     del eng
     torch.cuda.empty_cache()
+    if args.other_configs:
+        out["other_configs"] = {}
+        for n in ("c1_320x240_d64_r4", "c3_1920x1080_d256_r8"):
+            log(f"workload {n}")
+            out["other_configs"][n] = other_config(args, torch, sgm, datagen, dev, n, digest)
     if args.batch_reps > 0:
+        log("batched form: tuning, plan, replays, plain launches")
         out["batched"] = batched_form(args, torch, dev, sgm, datagen)
     if args.serve_seconds > 0:
+        log(f"served form: {args.serve_seconds:g} s trace, then the tight-budget and overload traces")
         out["served"] = served_form(args, torch, sgm, datagen)
     if args.cpu_frames > 0:
-        out["cpu_baseline"] = cpu_baseline(pair, cfg, args.cpu_frames)
+        log(f"CPU oracle: {args.cpu_frames} frame(s) single-threaded, then all cores")
+        out["cpu_baseline"] = cpu_baseline(fr, args.cpu_frames)
     print(json.dumps(out), flush=True)
 
 

@@ -22,6 +22,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgm_oracle.so")
 SRC_PATH = os.path.join(HERE, "sgm_oracle.c")
+MT_SRC_PATH = os.path.join(HERE, "sgm_oracle_mt.c")
 INVALID = 0xFFFF
 
 # Step r of each path; the predecessor of p is p - r.  First four: the
@@ -30,12 +31,13 @@ DIRECTIONS = ((1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, 1), (1, -1), (-1, -
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C99, -O2, no vector intrinsics)."""
+    """Compile the oracle with gcc (plain C99, -O2, no vector intrinsics; the
+    threaded driver with POSIX threads)."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-ffp-contract=off", "-shared",
-             "-fPIC", SRC_PATH, "-o", tmp, "-lm"])
+            ["gcc", "-O2", "-std=gnu99", "-Wall", "-Wextra", "-ffp-contract=off", "-shared",
+             "-fPIC", "-pthread", SRC_PATH, MT_SRC_PATH, "-o", tmp, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -66,6 +68,8 @@ def _load():
         lib.sgm_oracle_map_reduce_argmin.restype = I
         lib.sgm_oracle_ncc_cost.argtypes = [P, P, I, I, I, I, P]
         lib.sgm_oracle_ncc_cost.restype = None
+        lib.sgm_oracle_run_threaded.argtypes = [P, P, I, I, I, I, I, I, I, I, I, I, I, P, P, P]
+        lib.sgm_oracle_run_threaded.restype = I
         for name in ("sgm_oracle_census", "sgm_oracle_cost", "sgm_oracle_path",
                      "sgm_oracle_aggregate", "sgm_oracle_aggregate_at",
                      "sgm_oracle_wta", "sgm_oracle_right_disparity",
@@ -234,6 +238,26 @@ def run(left: np.ndarray, right: np.ndarray, params: Params) -> dict:
         d = median3x3(d)
     return {"census_left": cl, "census_right": cr, "cost": c, "agg": agg,
             "disp_left": dl, "disp_right": dr, "disp": d}
+
+
+def run_threaded(left: np.ndarray, right: np.ndarray, params: Params, nthreads: int) -> dict:
+    """run() with its independent work spread over nthreads threads (the
+    oracle's own functions on independent rows, images and path lines); for
+    timing on all host cores.  D^L, D^R and D equal run()'s bit for bit."""
+    _check_penalties(params.npaths, params.p1, params.p2)
+    a = _c(left, np.uint8)
+    b = _c(right, np.uint8)
+    h, w = a.shape
+    dl = np.empty((h, w), np.uint16)
+    dr = np.empty((h, w), np.uint16)
+    d = np.empty((h, w), np.uint16)
+    rc = _load().sgm_oracle_run_threaded(_ptr(a), _ptr(b), w, h, params.win_w, params.win_h,
+                                         params.ndisp, params.npaths, params.p1, params.p2,
+                                         params.lr_tolerance, int(bool(params.median3x3)),
+                                         int(nthreads), _ptr(dl), _ptr(dr), _ptr(d))
+    if rc != 0:
+        raise MemoryError("oracle: out of memory")
+    return {"disp_left": dl, "disp_right": dr, "disp": d}
 
 
 # ---------------------------------------------------------------------------

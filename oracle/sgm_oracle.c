@@ -88,8 +88,8 @@ void sgm_oracle_cost(const uint64_t* census_left, const uint64_t* census_right,
  * every d' with |d - d'| <= 1 also appears in the P2 term with a penalty no
  * smaller than its own.  `prev` is NULL at the first pixel of a path, where
  * L_r = S. */
-static void path_step(const uint8_t* cost_p, const uint16_t* prev, int ndisp,
-                      int p1, int p2, uint16_t* cur) {
+void sgm_oracle_path_step(const uint8_t* cost_p, const uint16_t* prev, int ndisp,
+                          int p1, int p2, uint16_t* cur) {
     if (prev == NULL) {
         for (int d = 0; d < ndisp; ++d) cur[d] = cost_p[d];
         return;
@@ -120,7 +120,7 @@ void sgm_oracle_path(const uint8_t* cost, int width, int height, int ndisp,
             const uint16_t* prev = NULL;
             if (inside(px, py, width, height))
                 prev = path_out + ((size_t)py * width + px) * ndisp;
-            path_step(cost + idx * ndisp, prev, ndisp, p1, p2,
+            sgm_oracle_path_step(cost + idx * ndisp, prev, ndisp, p1, p2,
                       path_out + idx * ndisp);
         }
     }
@@ -167,7 +167,7 @@ void sgm_oracle_aggregate_at(const uint8_t* cost, int width, int height, int ndi
         uint16_t* prev = NULL;
         uint16_t* cur = a;
         for (;;) {
-            path_step(cost + ((size_t)sy * width + sx) * ndisp, prev, ndisp, p1, p2, cur);
+            sgm_oracle_path_step(cost + ((size_t)sy * width + sx) * ndisp, prev, ndisp, p1, p2, cur);
             if (sx == x && sy == y) break;
             prev = cur;
             cur = (cur == a) ? b : a;

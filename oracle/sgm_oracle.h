@@ -32,6 +32,11 @@ void sgm_oracle_census(const uint8_t* img, int width, int height,
 void sgm_oracle_cost(const uint64_t* census_left, const uint64_t* census_right,
                      int width, int height, int ndisp, uint8_t* cost);
 
+/* One step of Eq. (sgm_path) at one pixel: L_r(p, .) from the cost vector of p
+ * and L_r(p - r, .) (`prev`, NULL at the first pixel of a path). */
+void sgm_oracle_path_step(const uint8_t* cost_p, const uint16_t* prev, int ndisp,
+                          int p1, int p2, uint16_t* cur);
+
 /* One SGM path L_r of Eq. (sgm_path), normalised by the predecessor's minimum,
  * for the step r = (dx, dy): the predecessor of p is p - r. */
 void sgm_oracle_path(const uint8_t* cost, int width, int height, int ndisp,
@@ -75,6 +80,17 @@ int sgm_oracle_map_reduce_argmin(const uint16_t* values, int n);
 #ifdef __cplusplus
 }
 #endif
+/* The whole path of oracle.run (census, cost, S_bar, D^L, D^R, LR check when
+ * lr_tolerance >= 0, median when median3x3) with its independent work spread
+ * over `nthreads` threads: the two census maps, rows of the cost volume and
+ * of the per-pixel selection steps, and the lines of each path direction.
+ * Same functions, same results; for timing the oracle on all host cores.
+ * Returns 0, or -1 when memory runs out. */
+int sgm_oracle_run_threaded(const uint8_t* left, const uint8_t* right, int width, int height,
+                            int win_w, int win_h, int ndisp, int npaths, int p1, int p2,
+                            int lr_tolerance, int median3x3, int nthreads,
+                            uint16_t* disp_left, uint16_t* disp_right, uint16_t* disp);
+
 /* Inverted, truncated NCC cost over win x win patches (win 5 or 9). */
 void sgm_oracle_ncc_cost(const uint8_t* left, const uint8_t* right, int width, int height,
                          int win, int ndisp, uint8_t* cost);

@@ -4,7 +4,9 @@
 
 Every source is compiled by hipcc for gfx950 only, in-tree, into
 ``paper_2106_07927_amd/libsgm.so``.  Packed-FP32 instruction selection is
-switched off for the device code.
+switched off for the device code.  ``paths.hip`` (the path pass) is compiled
+once per lane layout (-DSGM_PATH_LAYOUT=k), so its kernels build in
+parallel.
 """
 from __future__ import annotations
 
@@ -23,6 +25,10 @@ LIB = os.path.join(PKG, "libsgm.so")
 
 HIP_SOURCES = ["census.hip", "cost.hip", "ncc.hip", "aggregate.hip", "wta_lrc.hip"]
 CPP_SOURCES = ["sgm_capi.cpp", "batch.cpp"]
+PATH_LAYOUTS = 12          # entries of kPathLayouts in sgm_internal.h
+# (source, object, extra flags) of every translation unit
+UNITS = ([(s, s + ".o", []) for s in HIP_SOURCES + CPP_SOURCES] +
+         [("paths.hip", f"paths_{k}.hip.o", [f"-DSGM_PATH_LAYOUT={k}"]) for k in range(PATH_LAYOUTS)])
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I", INCLUDE, "-I", CSRC]
@@ -35,9 +41,10 @@ def _hipcc():
     return path if os.path.exists(path) else "hipcc"
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *COMMON]
+def _compile(unit) -> str:
+    src, objname, extra = unit
+    obj = os.path.join(BUILD, objname)
+    cmd = [_hipcc(), *COMMON, *extra]
     if src.endswith(".hip"):
         cmd += ["-x", "hip", *DEVICE, "-Rpass-analysis=kernel-resource-usage"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -65,9 +72,11 @@ def _check_resources(src: str, remarks: str) -> None:
         raise RuntimeError(f"{src}: kernels with scratch memory:\n  " + "\n  ".join(bad))
 
 
-def _stale(src: str) -> bool:
-    """True when src's object is missing or older than src or any header."""
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _stale(unit) -> bool:
+    """True when the unit's object is missing or older than its source or any
+    header."""
+    src, objname, _ = unit
+    obj = os.path.join(BUILD, objname)
     if not os.path.exists(obj):
         return True
     deps = [os.path.join(CSRC, src)]
@@ -80,11 +89,11 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     """Compile every source (with incremental=True: only those whose object is
     out of date) and link libsgm.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    sources = HIP_SOURCES + CPP_SOURCES
-    todo = [s for s in sources if not incremental or _stale(s)]
-    with ThreadPoolExecutor(max_workers=min(max(len(todo), 1), 8)) as pool:
+    todo = [u for u in UNITS if not incremental or _stale(u)]
+    workers = max(1, min(len(todo), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
         list(pool.map(_compile, todo))
-    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in sources]
+    objs = [os.path.join(BUILD, u[1]) for u in UNITS]
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)

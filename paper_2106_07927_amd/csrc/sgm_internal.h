@@ -43,39 +43,34 @@ __device__ __forceinline__ uint4 load_once16(const void* p) {
 }
 
 // ---------------------------------------------------------------------------
-// Path sum of 16 consecutive volume elements (Eq. sgm_path_aggr) from uint8
-// penalty slices: S = NP * C + sum_r A_r, with A_r = L_r - C in [0, P2].
-// Bytes are split into even / odd 16-bit lanes, so plain 32-bit adds carry
-// two sums per register with no carry between them (S <= NP * (255 + P2) <
-// 2^16).  With PAIR (P2 <= 127) two slices are first added bytewise: each
-// byte sum is at most 254, so no carry crosses a byte either.  `out` holds the
-// 16 sums as packed pairs in memory order.
+// Path slices.  The path pass writes one slice per pair of opposite
+// directions (r, -r).  With P2 <= 127 a slice holds A_r + A_-r, the sum of
+// the two penalty parts A = L - C in [0, P2], as uint8 (exact: at most 254);
+// otherwise it holds L_r + L_-r as uint16 (exact: npaths (255 + P2) < 2^16).
 // ---------------------------------------------------------------------------
-template <int NP, bool PAIR>
-__device__ __forceinline__ void merge16(const uint4& c, const uint4 (&a)[NP], uint32_t (&out)[8]) {
+__host__ __device__ inline bool slices_u8(int p2) { return p2 <= 127; }
+
+// Path sum of 16 consecutive volume elements (Eq. sgm_path_aggr) from NS
+// uint8 pair slices: S = MUL * C + sum of the slices, MUL = npaths.  Bytes
+// are split into even / odd 16-bit lanes, so plain 32-bit adds carry two
+// sums per register with no carry between them (S <= 8 * 255 + 4 * 254 <
+// 2^16).  `out` holds the 16 sums as packed pairs in memory order.
+template <int NS, int MUL>
+__device__ __forceinline__ void merge16(const uint4& c, const uint4 (&a)[NS], uint32_t (&out)[8]) {
     const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
     uint32_t ev[4], od[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        ev[q] = (cw[q] & 0x00FF00FFu) * (uint32_t)NP;
-        od[q] = ((cw[q] >> 8) & 0x00FF00FFu) * (uint32_t)NP;
+        ev[q] = (cw[q] & 0x00FF00FFu) * (uint32_t)MUL;
+        od[q] = ((cw[q] >> 8) & 0x00FF00FFu) * (uint32_t)MUL;
     }
-    constexpr int STEP = PAIR ? 2 : 1;
 #pragma unroll
-    for (int r = 0; r < NP; r += STEP) {
+    for (int r = 0; r < NS; ++r) {
         const uint32_t aw[4] = {a[r].x, a[r].y, a[r].z, a[r].w};
-        uint32_t sw[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sw[q] = aw[q];
-        if constexpr (PAIR) {
-            const uint32_t bw[4] = {a[r + 1].x, a[r + 1].y, a[r + 1].z, a[r + 1].w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sw[q] += bw[q];
-        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            ev[q] += sw[q] & 0x00FF00FFu;
-            od[q] += (sw[q] >> 8) & 0x00FF00FFu;
+            ev[q] += aw[q] & 0x00FF00FFu;
+            od[q] += (aw[q] >> 8) & 0x00FF00FFu;
         }
     }
     // interleave back: elements e0 o0 e1 o1 of every source word
@@ -83,6 +78,25 @@ __device__ __forceinline__ void merge16(const uint4& c, const uint4 (&a)[NP], ui
     for (int q = 0; q < 4; ++q) {
         out[2 * q] = __builtin_amdgcn_perm(od[q], ev[q], 0x05040100u);
         out[2 * q + 1] = __builtin_amdgcn_perm(od[q], ev[q], 0x07060302u);
+    }
+}
+
+// Path sum of 16 consecutive volume elements from NS uint16 pair slices
+// (two 16-byte blocks each): S = sum of the slices.
+template <int NS>
+__device__ __forceinline__ void wide_sum16(const uint4 (&a)[NS][2], uint32_t (&out)[8]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint32_t s[4] = {a[0][h].x, a[0][h].y, a[0][h].z, a[0][h].w};
+#pragma unroll
+        for (int r = 1; r < NS; ++r) {
+            s[0] = pk_add(s[0], a[r][h].x);
+            s[1] = pk_add(s[1], a[r][h].y);
+            s[2] = pk_add(s[2], a[r][h].z);
+            s[3] = pk_add(s[3], a[r][h].w);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[4 * h + q] = s[q];
     }
 }
 
@@ -243,6 +257,54 @@ struct PathLayout {
     int nreg_h, lpl_h;    // horizontal lines
     int nreg_o, lpl_o;    // vertical and diagonal lines
 };
+
+// Every layout the library builds (paths.hip is compiled once per entry).
+constexpr int kNumPathLayouts = 12;
+constexpr PathLayout kPathLayouts[kNumPathLayouts] = {
+    {1, 1, 1, 1}, {1, 2, 2, 1}, {1, 4, 4, 1}, {1, 8, 4, 2}, {1, 16, 4, 4}, {1, 32, 4, 8},
+    {2, 16, 4, 8}, {1, 64, 4, 16}, {2, 32, 4, 16}, {1, 64, 8, 8}, {2, 64, 8, 16}, {4, 32, 8, 16},
+};
+
+// The path pass for layout kPathLayouts[ID] (one object per layout): the
+// single-frame kernel when `one` is set, else the work-list kernel.
+template <int ID>
+hipError_t launch_paths_layout_id(const Frame* one, const WorkList* wl, int ndisp, bool u8,
+                                  int nblocks, hipStream_t stream);
+#define SGM_DECLARE_PATH_LAYOUT(K)                                                             \
+    template <>                                                                                \
+    hipError_t launch_paths_layout_id<K>(const Frame*, const WorkList*, int, bool, int, hipStream_t);
+SGM_DECLARE_PATH_LAYOUT(0)
+SGM_DECLARE_PATH_LAYOUT(1)
+SGM_DECLARE_PATH_LAYOUT(2)
+SGM_DECLARE_PATH_LAYOUT(3)
+SGM_DECLARE_PATH_LAYOUT(4)
+SGM_DECLARE_PATH_LAYOUT(5)
+SGM_DECLARE_PATH_LAYOUT(6)
+SGM_DECLARE_PATH_LAYOUT(7)
+SGM_DECLARE_PATH_LAYOUT(8)
+SGM_DECLARE_PATH_LAYOUT(9)
+SGM_DECLARE_PATH_LAYOUT(10)
+SGM_DECLARE_PATH_LAYOUT(11)
+#undef SGM_DECLARE_PATH_LAYOUT
+
+// Pairs of opposite path directions.  Pair q's forward step r (the reverse
+// wave walks -r): pairs 0, 1 are the 4-path set (Sec. 3.1.4), pairs 2, 3 add
+// the diagonals.  Pair 0 has one line per row, the others one per column
+// (the diagonals' lines wrap at the left / right border).
+__host__ __device__ inline void pair_dir(int q, int* dx, int* dy) {
+    constexpr int kDirs[4][2] = {{1, 0}, {0, 1}, {1, 1}, {-1, 1}};
+    *dx = kDirs[q][0];
+    *dy = kDirs[q][1];
+}
+
+__host__ __device__ inline int pair_lines(int q, int width, int height) { return q == 0 ? height : width; }
+
+// Blocks of pair q in the path pass: one block (the forward and the reverse
+// waves of two line groups) per two waves' worth of lines.
+__host__ __device__ inline int pair_blocks(int q, int width, int height, int lpl_h, int lpl_o) {
+    const int lpb = 2 * (64 / (q == 0 ? lpl_h : lpl_o));
+    return (pair_lines(q, width, height) + lpb - 1) / lpb;
+}
 int path_variants(int ndisp);                       // number of variants (>= 1)
 int default_variant(int width, int height, int ndisp);
 PathLayout path_layout(int ndisp, int variant);

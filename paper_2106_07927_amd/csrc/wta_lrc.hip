@@ -265,19 +265,21 @@ __device__ __forceinline__ void select_block(SelectTile<FINE>& st, const uint16_
 // ---- path sum fused with the selection pass --------------------------------
 // A block owns a tile of one row: 64 pixels, or 32 when D > 128, so that the
 // tile holds at most 8192 volume elements.
-//  (1) Each of its 256 threads loads two 16-byte blocks of the tile from the
-//      cost volume and from every uint8 penalty slice -- all loads issued
-//      before any is used -- and sums them (merge16) into an LDS copy of
-//      S_bar: one row of D values per pixel, padded by one dword so that rows
-//      start in different banks.  S_bar never goes to HBM.
+//  (1) Each of its 256 threads loads two blocks of 16 elements of the tile
+//      from every pair slice (and, for uint8 slices, from the cost volume)
+//      -- all loads issued before any is used -- and sums them into an LDS
+//      copy of S_bar: one row of D values per pixel, padded by one dword so
+//      that rows start in different banks.  S_bar never goes to HBM.
 //  (2) 256 / tile threads per pixel take the minimum key (S_bar << 8) | d
 //      over their share of the disparities; a DPP reduction gives D^L (and
 //      with FINE the refined value, from the winner's two neighbours in LDS).
 //  (3) One thread per right-view pixel q folds key(q + d, d) over the d with
 //      q + d inside the tile and merges that partial minimum into the D^R key
 //      map with atomicMin; the tiles holding q .. q + D - 1 complete it.
-// Needs D % 16 == 0, so every 16-byte block lies inside one pixel's vector.
-template <int NP, bool PAIR, bool FINE>
+// Needs D % 16 == 0, so every block of 16 elements lies inside one pixel's
+// vector.  NS pair slices: uint8 (S_bar = 2 NS C + sum) or uint16 (S_bar =
+// sum).
+template <int NS, bool U8, bool FINE>
 __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, const Frame& f, int bx,
                                                   int y) {
     const int width = f.width, ndisp = f.ndisp;
@@ -290,32 +292,59 @@ __device__ __forceinline__ void select_tile_block(uint16_t* __restrict__ sb, con
     const uint32_t e_last = (uint32_t)(row + x0 + npx) * (uint32_t)ndisp - 16u;
 
     // (1) path sum into LDS.  Blocks past the row's last pixel re-read its
-    // last block and land in LDS rows that are never read.
+    // last block and land in LDS rows that are never read.  The slices are
+    // read once (nontemporal loads); the cost volume keeps cached loads.
     const int nblk = tpx * ndisp / 16;             // <= 512
-    uint4 c[2];
-    uint4 a[2][NP];
-    // the slices are read once (nontemporal loads: 123 -> 83 us at
-    // 1242x375, D = 128, 8 paths); the cost volume keeps cached loads
+    if constexpr (U8) {
+        uint4 c[2];
+        uint4 a[2][NS];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        if (256 * i >= nblk) break;                // uniform: small D fits in one pass
-        const uint32_t e = min(e_tile + 16u * (uint32_t)(threadIdx.x + 256 * i), e_last);
-        c[i] = *reinterpret_cast<const uint4*>(f.cost + e);
+        for (int i = 0; i < 2; ++i) {
+            if (256 * i >= nblk) break;            // uniform: small D fits in one pass
+            const uint32_t e = min(e_tile + 16u * (uint32_t)(threadIdx.x + 256 * i), e_last);
+            c[i] = *reinterpret_cast<const uint4*>(f.cost + e);
 #pragma unroll
-        for (int r = 0; r < NP; ++r)
-            a[i][r] = load_once16(f.slices + (size_t)r * f.slice_stride + e);
-    }
+            for (int r = 0; r < NS; ++r)
+                a[i][r] = load_once16(f.slices + (size_t)r * f.slice_stride + e);
+        }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int b = threadIdx.x + 256 * i;
-        if (b < nblk) {
-            uint32_t sum[8];
-            merge16<NP, PAIR>(c[i], a[i], sum);
-            const int p = (16 * b) / ndisp;
-            const int d = 16 * b - p * ndisp;
-            uint32_t* dst = reinterpret_cast<uint32_t*>(sb + p * rs + d);
+        for (int i = 0; i < 2; ++i) {
+            const int b = threadIdx.x + 256 * i;
+            if (b < nblk) {
+                uint32_t sum[8];
+                merge16<NS, 2 * NS>(c[i], a[i], sum);
+                const int p = (16 * b) / ndisp;
+                const int d = 16 * b - p * ndisp;
+                uint32_t* dst = reinterpret_cast<uint32_t*>(sb + p * rs + d);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) dst[k] = sum[k];
+                for (int k = 0; k < 8; ++k) dst[k] = sum[k];
+            }
+        }
+    } else {
+        const uint16_t* slices = reinterpret_cast<const uint16_t*>(f.slices);
+        uint4 a[2][NS][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            if (256 * i >= nblk) break;
+            const uint32_t e = min(e_tile + 16u * (uint32_t)(threadIdx.x + 256 * i), e_last);
+#pragma unroll
+            for (int r = 0; r < NS; ++r) {
+                a[i][r][0] = load_once16(slices + (size_t)r * f.slice_stride + e);
+                a[i][r][1] = load_once16(slices + (size_t)r * f.slice_stride + e + 8);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int b = threadIdx.x + 256 * i;
+            if (b < nblk) {
+                uint32_t sum[8];
+                wide_sum16<NS>(a[i], sum);
+                const int p = (16 * b) / ndisp;
+                const int d = 16 * b - p * ndisp;
+                uint32_t* dst = reinterpret_cast<uint32_t*>(sb + p * rs + d);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) dst[k] = sum[k];
+            }
         }
     }
     __syncthreads();
@@ -369,13 +398,13 @@ __host__ __device__ inline size_t fused_lds_bytes(int ndisp) {
     return (size_t)fused_tile_px(ndisp) * (size_t)(ndisp + 2) * sizeof(uint16_t);
 }
 
-template <int NP, bool PAIR, bool FINE>
+template <int NS, bool U8, bool FINE>
 __global__ __launch_bounds__(256) void select_fused_kernel(Frame f) {
     extern __shared__ uint16_t sb[];
-    select_tile_block<NP, PAIR, FINE>(sb, f, blockIdx.x, blockIdx.y);
+    select_tile_block<NS, U8, FINE>(sb, f, blockIdx.x, blockIdx.y);
 }
 
-template <int NP, bool PAIR>
+template <int NS, bool U8>
 __global__ __launch_bounds__(256) void select_fused_batch_kernel(WorkList wl) {
     extern __shared__ uint16_t sb[];
     for (int b = blockIdx.x; b < wl.total; b += gridDim.x) {
@@ -383,7 +412,7 @@ __global__ __launch_bounds__(256) void select_fused_batch_kernel(WorkList wl) {
         const Frame& f = wl.frames[fi];
         const int lb = b - wl.starts[fi];
         const int bxs = fused_blocks_x(f.width, f.ndisp);
-        select_tile_block<NP, PAIR, false>(sb, f, lb % bxs, lb / bxs);
+        select_tile_block<NS, U8, false>(sb, f, lb % bxs, lb / bxs);
     }
 }
 
@@ -573,14 +602,14 @@ void launch_select_any(const Frame* one, const WorkList* wl, int ndisp, hipStrea
     }
 }
 
-template <int NP, bool PAIR, bool FINE>
+template <int NS, bool U8, bool FINE>
 void launch_fused_t(const Frame* one, const WorkList* wl, int ndisp, hipStream_t stream) {
     const size_t lds = fused_lds_bytes(ndisp);
     if (one) {
         const dim3 g(fused_blocks_x(one->width, ndisp), one->height);
-        select_fused_kernel<NP, PAIR, FINE><<<g, 256, lds, stream>>>(*one);
+        select_fused_kernel<NS, U8, FINE><<<g, 256, lds, stream>>>(*one);
     } else {
-        select_fused_batch_kernel<NP, PAIR><<<persistent_grid(wl->total), 256, lds, stream>>>(*wl);
+        select_fused_batch_kernel<NS, U8><<<persistent_grid(wl->total), 256, lds, stream>>>(*wl);
     }
 }
 
@@ -588,13 +617,13 @@ void launch_fused_t(const Frame* one, const WorkList* wl, int ndisp, hipStream_t
 template <bool FINE>
 void launch_fused_any(const Frame* one, const WorkList* wl, int ndisp, int npaths, int p2,
                       hipStream_t stream) {
-    const bool pair = p2 <= 127;
+    const bool u8 = slices_u8(p2);
     if (npaths == 4) {
-        if (pair) launch_fused_t<4, true, FINE>(one, wl, ndisp, stream);
-        else launch_fused_t<4, false, FINE>(one, wl, ndisp, stream);
+        if (u8) launch_fused_t<2, true, FINE>(one, wl, ndisp, stream);
+        else launch_fused_t<2, false, FINE>(one, wl, ndisp, stream);
     } else {
-        if (pair) launch_fused_t<8, true, FINE>(one, wl, ndisp, stream);
-        else launch_fused_t<8, false, FINE>(one, wl, ndisp, stream);
+        if (u8) launch_fused_t<4, true, FINE>(one, wl, ndisp, stream);
+        else launch_fused_t<4, false, FINE>(one, wl, ndisp, stream);
     }
 }
 
@@ -671,7 +700,8 @@ __global__ __launch_bounds__(256) void check_median_fine_kernel(Frame f) {
 }  // namespace
 
 bool fused_select_supported(int ndisp, int npaths, int p2) {
-    return ndisp % 16 == 0 && ndisp <= 256 && p2 <= 255 && (npaths == 4 || npaths == 8);
+    (void)p2;
+    return ndisp % 16 == 0 && ndisp <= 256 && (npaths == 4 || npaths == 8);
 }
 
 hipError_t launch_aggregate_select(const Frame& f, hipStream_t stream, bool fine) {

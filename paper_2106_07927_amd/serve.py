@@ -154,11 +154,12 @@ def slot_bytes(spec: StreamSpec, npaths: int, p2: int) -> int:
     to 256 bytes: the two input images, both census maps, the cost volume,
     the two disparity maps, and the workspace of the streamlined aggregation
     (path slices, S_bar only where the fused selection does not apply, D^R
-    keys, D^L)."""
+    keys, D^L); one path slice per pair of opposite directions, uint8 for
+    P2 <= 127, else uint16."""
     n = spec.width * spec.height
     nd = spec.ndisp
-    slices = npaths * _a256(n * nd) * (1 if p2 <= 255 else 2)
-    fused = nd % 16 == 0 and nd <= 256 and p2 <= 255
+    slices = npaths // 2 * _a256(n * nd) * (1 if p2 <= 127 else 2)
+    fused = nd % 16 == 0 and nd <= 256
     work = _a256(slices) + (0 if fused else _a256(2 * n * nd)) + _a256(4 * n) + _a256(2 * n)
     return 2 * _a256(n) + 2 * _a256(8 * n) + _a256(n * nd) + 2 * _a256(2 * n) + _a256(work)
 
@@ -232,9 +233,11 @@ class Server:
         self.used_bytes += self.sizes[s]
         return slot
 
-    def run(self, trace: List[Request], keep=None) -> Stats:
+    def run(self, trace: List[Request], keep=None, release: bool = True) -> Stats:
         """Serves the trace; `keep(request)` says whether to copy a result to
-        the host for checking (the backend keeps it in result_of)."""
+        the host for checking (the backend keeps it in result_of).  With
+        `release` the slots go back to the backend at the end, so that
+        another server can use its memory; else they stay for the next run."""
         stats = Stats()
         for s, size in enumerate(self.sizes):
             if size > self.budget:
@@ -263,6 +266,7 @@ class Server:
             inflight = still
             # admission: oldest waiting head first, per-stream FIFO
             heads = sorted((q[0].arrival, s) for s, q in pending.items() if q)
+            admitted = False
             for _, s in heads:
                 if len(inflight) >= self.hip_streams:
                     break
@@ -278,13 +282,34 @@ class Server:
                 slot["job"] = handle
                 inflight.append({"req": req, "slot": slot, "handle": handle, "start": now})
                 stats.peak_bytes = max(stats.peak_bytes, self.used_bytes)
+                admitted = True
+            if heads and not admitted and not inflight:
+                # nothing runs and nothing could be admitted: every slot is
+                # idle and eviction already failed, so no later pass can
+                # succeed (the backend's memory is held by someone else);
+                # reject the oldest waiting frame instead of waiting forever
+                _, s = heads[0]
+                pending[s].popleft()
+                stats.rejected += 1
+                continue
             next_arrival = trace[i].arrival if i < len(trace) else None
             if next_arrival is not None and not inflight and not any(pending.values()):
                 self.backend.wait_until(next_arrival)
             else:
                 self.backend.idle(next_arrival)
         stats.evictions = self.evictions
+        if release:
+            self.close()
         return stats
+
+    def close(self):
+        """Returns every slot of this server to the backend (all are idle
+        once run() has drained its trace)."""
+        for s in list(self.slots):
+            for slot in self.slots[s]:
+                self.backend.free_slot(slot["handle"])
+                self.used_bytes -= self.sizes[s]
+            self.slots[s] = []
 
 
 class FakeBackend:

@@ -109,8 +109,10 @@ def test_aggregate_validation(lib):
     assert f(P(FAKE), 32768, 32768, 4, 8, 10, 120, P(FAKE), P(FAKE), W(big), P(NULL)) == ARG  # volume
     assert f(P(FAKE), 8, 8, 16, 8, 10, 120, P(FAKE), P(NULL), W(big), P(NULL)) == WS
     need = lib.sgm_aggregate_work_bytes(8, 8, 16, 8, 120)
-    assert need == 8 * 1024                                    # 8 slices of 1024 uint8
-    assert lib.sgm_aggregate_work_bytes(8, 8, 16, 8, 256) == 8 * 1024 * 2
+    assert need == 4 * 1024                      # 4 pair slices of 1024 uint8 (P2 <= 127)
+    assert lib.sgm_aggregate_work_bytes(8, 8, 16, 8, 127) == 4 * 1024
+    assert lib.sgm_aggregate_work_bytes(8, 8, 16, 8, 128) == 4 * 1024 * 2   # uint16 beyond
+    assert lib.sgm_aggregate_work_bytes(8, 8, 16, 4, 256) == 2 * 1024 * 2
     assert lib.sgm_aggregate_work_bytes(8, 8, 16, 8, 7937) == 0
     assert f(P(FAKE), 8, 8, 16, 8, 10, 120, P(FAKE), P(FAKE), W(need - 1), P(NULL)) == WS
     assert f(P(FAKE + 8), 8, 8, 16, 8, 10, 120, P(FAKE), P(FAKE), W(need), P(NULL)) == ALIGN
@@ -148,20 +150,20 @@ def test_aggregate_select_validation(lib):
     assert f(*args(nd=0)) == ARG
     assert f(*args(med=2)) == ARG
     assert f(*args(work=NULL)) == WS
-    # fused form (D % 16 == 0, P2 <= 255): slices, D^R keys, D^L; no S_bar
+    # fused form (D % 16 == 0): pair slices, D^R keys, D^L; no S_bar
     n = 8 * 8
     need = lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 120)
-    assert need == 8 * 1024 + 256 + 256
+    assert need == 4 * 1024 + 256 + 256
     assert f(*args(wb=need - 1)) == WS
     assert f(*args(work=FAKE + 16, wb=need)) == ALIGN           # 256-byte alignment
     assert f(*args(cost=FAKE + 8, wb=need)) == ALIGN
     assert f(*args(out=FAKE + 2, wb=need)) == ALIGN
     assert f(*args(outr=FAKE + 2, wb=need)) == ALIGN
-    # unfused fallbacks also hold S_bar in the workspace
+    # the unfused fallback (D % 16 != 0) also holds S_bar in the workspace
     assert lib.sgm_aggregate_select_work_bytes(8, 8, 15, 8, 120) == \
-        8 * 1024 + (2 * n * 15 + 255) // 256 * 256 + 256 + 256
-    assert lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 256) == \
-        8 * 2048 + 2048 + 256 + 256
+        4 * 1024 + (2 * n * 15 + 255) // 256 * 256 + 256 + 256
+    # P2 > 127: uint16 pair slices, still fused
+    assert lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 256) == 4 * 2048 + 256 + 256
     assert lib.sgm_aggregate_select_work_bytes(8, 8, 16, 8, 7937) == 0
 
 
@@ -204,10 +206,11 @@ def test_batch_validation(lib):
     pairs[0] = sgm.SgmPair(FAKE, FAKE, 64, 48, 64, 64, FAKE, None)
     pairs[1] = sgm.SgmPair(FAKE, FAKE, 32, 16, 40, 16, FAKE, FAKE)
     need = lib.sgm_batch_workspace_bytes(pairs, 2, ctypes.byref(prm), None)
-    # two frames of intermediates (census x2, cost, slices, keys, D^L; S_bar
-    # only for frames that cannot take the fused selection) plus tables
+    # two frames of intermediates (census x2, cost, one uint8 slice per pair
+    # of paths, keys, D^L; S_bar only for frames that cannot take the fused
+    # selection) plus tables
     n0, n1 = 64 * 48, 32 * 16
-    lower = sum(8 * 2 * n + n * nd + 8 * n * nd + 4 * n + 2 * n
+    lower = sum(8 * 2 * n + n * nd + 4 * n * nd + 4 * n + 2 * n
                 for n, nd in ((n0, 64), (n1, 16)))
     assert need >= lower
     # a tuning table that splits the path launches needs more table space

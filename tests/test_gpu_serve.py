@@ -91,6 +91,7 @@ def test_served_frames_equal_oracle_and_overlap(setup):
     assert torch.cuda.memory_allocated() == before, "serving allocated device memory"
     assert stats.served == len(trace) and stats.rejected == 0
     assert stats.peak_bytes <= backend.arena.capacity
+    assert backend.arena.used == 0, "the run did not hand its slots back"
     overlap = _overlapping_pairs(stats)
     say(f"served {stats.served}, overlapping pairs {overlap}, deferred {stats.deferred}")
     assert overlap > 0, "no two frames were in flight together"

@@ -20,7 +20,7 @@ def run(budget, hip_streams=8, duration=2.0, rate=30.0, mdes=1e5):
     trace = serve.make_trace(sp, rate, duration, 4, seed=5)
     be = FakeBackend(sp, mdes_per_s=mdes)
     srv = Server(sp, be, budget_bytes=budget, hip_streams=hip_streams)
-    return sp, trace, be, srv, srv.run(trace)
+    return sp, trace, be, srv, srv.run(trace, release=False)
 
 
 def test_every_request_served_once_and_fifo_per_stream():
@@ -120,9 +120,42 @@ def test_arena_fragmentation_forces_extra_evictions():
     trace = serve.make_trace(sp, 30.0, 2.0, 4, seed=21)
     be = FakeBackend(sp, mdes_per_s=2e4, arena_bytes=budget)
     srv = Server(sp, be, budget_bytes=budget, hip_streams=8)
-    st = srv.run(trace)
+    st = srv.run(trace, release=False)
     assert st.served == len(trace) and st.rejected == 0
     assert st.evictions > 0 and st.deferred > 0
     assert be.arena.used == sum(serve.Arena.round(srv.sizes[t]) for t, lst in srv.slots.items()
                                 for _ in lst)
     assert be.arena.used <= be.arena.capacity
+
+
+def test_servers_in_turn_share_one_arena():
+    """A run hands its slots back to the backend, so a second server on the
+    same arena can place its own (it used to wait forever for memory that
+    the first server still held)."""
+    sp = specs()
+    sizes = [serve.slot_bytes(s, 8, 120) for s in sp]
+    cap = serve.Arena.round(sum(serve.Arena.round(b) for b in sizes))
+    be = FakeBackend(sp, mdes_per_s=5e4, arena_bytes=cap)
+    trace = serve.make_trace(sp, 30.0, 1.0, 4, seed=31)
+    for _ in range(3):
+        st = Server(sp, be, budget_bytes=cap, hip_streams=4).run(trace)
+        assert st.served == len(trace) and st.rejected == 0
+        assert be.arena.used == 0 and be.arena.free == [(0, be.arena.capacity)]
+    assert be.allocs == be.frees
+
+
+def test_memory_held_elsewhere_rejects_instead_of_hanging():
+    """When the backend's arena is taken by someone else, frames that can
+    never get a slot are rejected; the run still ends."""
+    sp = specs()
+    sizes = [serve.slot_bytes(s, 8, 120) for s in sp]
+    cap = serve.Arena.round(sum(serve.Arena.round(b) for b in sizes))
+    be = FakeBackend(sp, mdes_per_s=5e4, arena_bytes=cap)
+    held = be.arena.alloc(cap - serve.Arena.round(min(sizes)))   # room for the smallest only
+    trace = serve.make_trace(sp, 30.0, 1.0, 4, seed=32)
+    st = Server(sp, be, budget_bytes=cap, hip_streams=4).run(trace)
+    small = int(np.argmin(sizes))
+    assert st.served == sum(1 for r in trace if r.stream == small)
+    assert st.rejected == len(trace) - st.served
+    be.arena.release(held, cap - serve.Arena.round(min(sizes)))
+    assert be.arena.used == 0
