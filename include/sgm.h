@@ -49,7 +49,8 @@ typedef enum {
     SGM_ERR_UNSUPPORTED = -2,  /* census window other than 5x5 or 9x7               */
     SGM_ERR_ALIGN = -3,        /* pointer not aligned as documented below           */
     SGM_ERR_HIP = -4,          /* a HIP launch failed; see sgm_last_hip_error()     */
-    SGM_ERR_WORKSPACE = -5     /* workspace missing or too small                    */
+    SGM_ERR_WORKSPACE = -5,    /* workspace missing or too small                    */
+    SGM_ERR_TOO_LARGE = -6     /* frame needs more than SGM_NOALLOC_SCRATCH_BYTES   */
 } sgm_status;
 
 /*
@@ -200,6 +201,30 @@ int32_t sgm_aggregate_select(const uint8_t* cost, int32_t width, int32_t height,
 /* Bytes of `work` that sgm_aggregate_select needs (0 on invalid arguments). */
 size_t sgm_aggregate_select_work_bytes(int32_t width, int32_t height, int32_t ndisp,
                                        int32_t npaths, int32_t p2);
+
+/*
+ * sgm_aggregate_select without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * hosts that forbid hipMalloc).  The workspace is a fixed array of
+ * SGM_NOALLOC_SCRATCH_BYTES inside this library, one per GPU, kept until the
+ * process ends; the call itself allocates nothing.  Outputs are bit-identical
+ * to sgm_aggregate_select with the same arguments.
+ *   Arguments, layouts and ownership as for sgm_aggregate_select, without
+ *   work / work_bytes; `stream` must belong to the current device.
+ *   Every call on one GPU uses that GPU's one array: calls that overlap on
+ *   one GPU (other streams, other host threads) race and must be ordered by
+ *   the caller; calls queued on one stream are ordered already.
+ * Errors: SGM_ERR_ARG, SGM_ERR_ALIGN, SGM_ERR_HIP (including the first
+ *         look-up of the array on a device), SGM_ERR_TOO_LARGE when
+ *         sgm_aggregate_select_work_bytes(...) > SGM_NOALLOC_SCRATCH_BYTES
+ *         (1242 x 375 with D = 128 and 8 paths needs about 241 MB and fits);
+ *         nothing is enqueued on error.
+ */
+#define SGM_NOALLOC_SCRATCH_BYTES (256u << 20)
+int32_t sgm_aggregate_select_noalloc(const uint8_t* cost, int32_t width, int32_t height,
+                                     int32_t ndisp, int32_t npaths, int32_t p1, int32_t p2,
+                                     int32_t lr_tolerance, int32_t median3x3,
+                                     uint16_t* disp_out, uint16_t* disp_right_out, void* stream);
 
 /*
  * sgm_aggregate_select with subpixel refinement (Sec. 2.1.3): every pixel's

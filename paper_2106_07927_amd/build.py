@@ -23,7 +23,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsgm.so")
 
-HIP_SOURCES = ["census.hip", "cost.hip", "ncc.hip", "aggregate.hip", "wta_lrc.hip"]
+HIP_SOURCES = ["census.hip", "cost.hip", "ncc.hip", "aggregate.hip", "wta_lrc.hip", "noalloc.hip"]
 CPP_SOURCES = ["sgm_capi.cpp", "batch.cpp"]
 PATH_LAYOUTS = 12          # entries of kPathLayouts in sgm_internal.h
 # (source, object, extra flags) of every translation unit

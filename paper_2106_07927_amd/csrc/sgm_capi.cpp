@@ -106,9 +106,14 @@ size_t exact_layout(int32_t width, int32_t height, int32_t ndisp, const sgm_para
 
 }  // namespace
 
+namespace sgm {
+// Records a HIP error for sgm_last_hip_error (other source files' entry points).
+int32_t record_hip_error(hipError_t e) { return hip_status(e); }
+}  // namespace sgm
+
 extern "C" {
 
-int32_t sgm_abi_version(void) { return 3; }
+int32_t sgm_abi_version(void) { return 4; }
 
 const char* sgm_status_string(int32_t status) {
     switch (status) {
@@ -119,6 +124,9 @@ const char* sgm_status_string(int32_t status) {
         case SGM_ERR_ALIGN: return "SGM_ERR_ALIGN: misaligned buffer";
         case SGM_ERR_HIP: return "SGM_ERR_HIP: HIP launch failed";
         case SGM_ERR_WORKSPACE: return "SGM_ERR_WORKSPACE: workspace missing or too small";
+        case SGM_ERR_TOO_LARGE:
+            return "SGM_ERR_TOO_LARGE: the frame needs more than the fixed scratch "
+                   "(SGM_NOALLOC_SCRATCH_BYTES)";
         default: return "unknown sgm status";
     }
 }

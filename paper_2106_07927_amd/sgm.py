@@ -28,9 +28,12 @@ SGM_ERR_UNSUPPORTED = -2
 SGM_ERR_ALIGN = -3
 SGM_ERR_HIP = -4
 SGM_ERR_WORKSPACE = -5
+SGM_ERR_TOO_LARGE = -6
+NOALLOC_SCRATCH_BYTES = 256 << 20      # SGM_NOALLOC_SCRATCH_BYTES
 
 EXPORTS = ("sgm_census", "sgm_census_pair", "sgm_cost", "sgm_cost_ncc", "sgm_aggregate",
            "sgm_aggregate_work_bytes", "sgm_wta_lrc", "sgm_wta_lrc_work_elems", "sgm_aggregate_select", "sgm_aggregate_select_work_bytes",
+           "sgm_aggregate_select_noalloc",
            "sgm_aggregate_select_subpixel", "sgm_aggregate_select_subpixel_work_bytes",
            "sgm_disparity_exact_lr", "sgm_disparity_exact_lr_work_bytes",
            "sgm_batch_workspace_bytes", "sgm_batch_plan_create",
@@ -92,6 +95,8 @@ def load_library(path: Optional[str] = None):
                                          ctypes.c_size_t, P]
     lib.sgm_aggregate_select_work_bytes.argtypes = [I32, I32, I32, I32, I32]
     lib.sgm_aggregate_select_work_bytes.restype = ctypes.c_size_t
+    lib.sgm_aggregate_select_noalloc.argtypes = [P, I32, I32, I32, I32, I32, I32, I32, I32, P, P, P]
+    lib.sgm_aggregate_select_noalloc.restype = I32
     lib.sgm_aggregate_select_subpixel.argtypes = lib.sgm_aggregate_select.argtypes
     lib.sgm_aggregate_select_subpixel.restype = I32
     lib.sgm_aggregate_select_subpixel_work_bytes.argtypes = [I32, I32, I32, I32, I32]
@@ -322,6 +327,32 @@ def sgm_aggregate_select(cost: torch.Tensor, npaths: int, p1: int, p2: int, lr_t
     _check(load_library().sgm_aggregate_select(_ptr(cost), w, h, nd, npaths, p1, p2, lr_tolerance,
                                                int(bool(median3x3)), _ptr(out), _ptr(out_right),
                                                _ptr(work), work.numel(), _stream(stream)))
+    return out, out_right
+
+
+def sgm_aggregate_select_noalloc(cost: torch.Tensor, npaths: int, p1: int, p2: int,
+                                 lr_tolerance: int, median3x3: bool,
+                                 out: Optional[torch.Tensor] = None,
+                                 out_right: Optional[torch.Tensor] = None,
+                                 want_right: bool = False, stream=None):
+    """sgm_aggregate_select with the library's fixed per-GPU scratch as its
+    workspace (no allocation in the call; frames needing more than
+    NOALLOC_SCRATCH_BYTES are rejected).  Calls that overlap on one GPU
+    race on that scratch.  Returns (disp, disp_right or None)."""
+    if cost.dtype != torch.uint8 or cost.dim() != 3:
+        raise ValueError("cost must be a 3-D uint8 tensor")
+    h, w, nd = cost.shape
+    if out is None:
+        out = _empty((h, w), torch.uint16, cost.device)
+    _expect(out, torch.uint16, (h, w), "out")
+    if want_right and out_right is None:
+        out_right = _empty((h, w), torch.uint16, cost.device)
+    if out_right is not None:
+        _expect(out_right, torch.uint16, (h, w), "out_right")
+    _check(load_library().sgm_aggregate_select_noalloc(_ptr(cost), w, h, nd, npaths, p1, p2,
+                                                       lr_tolerance, int(bool(median3x3)),
+                                                       _ptr(out), _ptr(out_right),
+                                                       _stream(stream)))
     return out, out_right
 
 

@@ -37,8 +37,8 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings_and_version(lib):
-    assert lib.sgm_abi_version() == 3
-    for code in (OK, ARG, UNSUP, ALIGN, HIP, WS):
+    assert lib.sgm_abi_version() == 4
+    for code in (OK, ARG, UNSUP, ALIGN, HIP, WS, sgm.SGM_ERR_TOO_LARGE):
         assert lib.sgm_status_string(code).decode().startswith("SGM_")
     assert lib.sgm_status_string(99) == b"unknown sgm status"
 
@@ -132,6 +132,32 @@ def test_wta_lrc_validation(lib):
     assert f(P(FAKE), 8, 8, 16, 1, 1, P(FAKE), P(FAKE + 2), P(FAKE), P(NULL)) == ALIGN
     assert lib.sgm_wta_lrc_work_elems(10, 20) == 3 * 200
     assert lib.sgm_wta_lrc_work_elems(0, 20) == 0
+
+
+def test_aggregate_select_noalloc_validation(lib):
+    """Every rejection happens before the first HIP call (none here needs a
+    GPU); a frame whose workspace exceeds the fixed scratch is refused."""
+    f = lib.sgm_aggregate_select_noalloc
+    args = lambda **k: [P(k.get("cost", FAKE)), k.get("w", 8), k.get("h", 8), k.get("nd", 16),
+                        k.get("npaths", 8), k.get("p1", 10), k.get("p2", 120), k.get("t", 1),
+                        k.get("med", 1), P(k.get("out", FAKE)), P(k.get("outr", NULL)), P(NULL)]
+    TOO_LARGE = sgm.SGM_ERR_TOO_LARGE
+    assert f(*args(cost=NULL)) == ARG
+    assert f(*args(out=NULL)) == ARG
+    assert f(*args(npaths=6)) == ARG
+    assert f(*args(p1=121)) == ARG
+    assert f(*args(nd=0)) == ARG
+    assert f(*args(med=2)) == ARG
+    assert f(*args(cost=FAKE + 8)) == ALIGN
+    assert f(*args(out=FAKE + 2)) == ALIGN
+    assert f(*args(outr=FAKE + 2)) == ALIGN
+    cap = sgm.NOALLOC_SCRATCH_BYTES
+    # 1242x375, D=128, 8 paths fits; 1920x1080, D=256 does not
+    assert lib.sgm_aggregate_select_work_bytes(1242, 375, 128, 8, 120) <= cap
+    assert lib.sgm_aggregate_select_work_bytes(1920, 1080, 256, 8, 120) > cap
+    assert f(*args(w=1920, h=1080, nd=256)) == TOO_LARGE
+    assert f(*args(w=1920, h=1080, nd=256, cost=FAKE + 8)) == TOO_LARGE   # size first
+    assert lib.sgm_status_string(TOO_LARGE).decode().startswith("SGM_ERR_TOO_LARGE")
 
 
 def test_aggregate_select_validation(lib):
