@@ -71,12 +71,13 @@ def parse():
 
 
 # Counter readings for the dominant unit at the 1242x375 / D=128 / 8-path
-# frame (profiles/), per call: HBM bytes from FETCH_SIZE and WRITE_SIZE, each
-# scaled by its reading for a plain copy of known size, and the VALU-busy
-# share of the path kernel from SQ_INSTS_VALU.  An entry holds only for the
-# kernel sources whose digest it names; otherwise the figures are null.
+# frame (profiles/), per call: HBM bytes (MB) from FETCH_SIZE and WRITE_SIZE,
+# each scaled by its reading for a plain copy of known size, and the VALU-busy
+# share of the call's kernels (SQ_INSTS_VALU x 4 cycles over 1024 SIMDs at
+# 2.4 GHz and the kernels' durations).  An entry holds only for the kernel
+# sources whose digest it names; otherwise the figures are null.
 COUNTERS = {
-    "sgm_aggregate_select": {"sources": None, "traffic": None, "valu_busy": None},
+    "sgm_aggregate_select": {"sources": "a106dad83c5fc01f", "traffic": 1475.5, "valu_busy": 0.606},
 }
 
 KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "paths.hip", "wta_lrc.hip",
@@ -409,7 +410,9 @@ def batched_form(args, torch, dev, sgm, datagen):
         lefts.append(torch.from_numpy(pair["left"]).to(dev))
         rights.append(torch.from_numpy(pair["right"]).to(dev))
     table, tune_ms = tune.tune([(w, h, nd) for (w, h, nd, _) in specs], params, device=dev)
-    plan = sgm.BatchPlan(lefts, rights, [s[2] for s in specs], params, tune_table=json.dumps(table))
+    ndisps = [s[2] for s in specs]
+    table, chains_ms = tune.tune_chains(lefts, rights, ndisps, params, table)
+    plan = sgm.BatchPlan(lefts, rights, ndisps, params, tune_table=json.dumps(table))
     plan.run()
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -449,8 +452,10 @@ def batched_form(args, torch, dev, sgm, datagen):
             "fps": round(len(specs) / batch_ms * 1e3, 1),
             "plain_ms_per_batch": round(plain_ms, 3), "plain_mdes": round(des / plain_ms / 1e3, 1),
             "speedup": round(plain_ms / batch_ms, 3), "tune_table": table, "tune_ms": tune_ms,
+            "chains_ms": chains_ms,
             "launch": "one hipGraph replay (work-list kernels for the small frames, the "
-                      "single-frame kernels for the others)"}
+                      "single-frame kernels for the others, spread over the tuned number of "
+                      "streams inside the graph)"}
 
 
 def served_form(args, torch, sgm, datagen):

@@ -293,11 +293,15 @@ size_t sgm_batch_workspace_bytes(const sgm_pair* pairs, int32_t n,
  * sgm_batch_workspace_bytes bytes, owned by the caller and kept alive with
  * the plan), copies the work lists to the device (a synchronous copy), and
  * captures the whole batch into a hipGraph on a stream of its own.
- * tune_table: NULL, or a JSON object mapping "WxHxD" to the path-kernel
- * lane-layout variant to use for pairs of that shape (written by the
- * project's tuner; other shapes use the library's default for their size,
- * as the single-frame calls do).  Variants never change
- * results.
+ * tune_table: NULL, or a flat JSON object (written by the project's tuner)
+ * with two kinds of entries:
+ *   "WxHxD": n   the path-kernel lane-layout variant for pairs of that shape
+ *                (other shapes use the library's default for their size, as
+ *                the single-frame calls do);
+ *   "chains": n  how many streams inside the graph the pairs of 100k pixels
+ *                and more are spread over, 1..8 (default 2); pairs on
+ *                different streams may overlap.
+ * Neither ever changes results.
  * Errors: SGM_ERR_ARG, SGM_ERR_WORKSPACE, SGM_ERR_ALIGN, SGM_ERR_HIP.
  */
 int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n,

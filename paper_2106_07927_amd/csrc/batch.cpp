@@ -9,17 +9,16 @@
 //     census (all frames, both images) -> cost (per D) -> paths (per D and
 //     variant) -> D^R key fill (all) -> path sum fused with the selection
 //     (per D) -> LR check + median (all)
-// Frames whose disparity range or penalties rule out the fused selection
-// (D % 16 != 0, P2 > 255) take merge (S_bar in the workspace) and the plain
-// selection instead.
+// Frames whose disparity range rules out the fused selection (D % 16 != 0)
+// take merge (S_bar in the workspace) and the plain selection instead.
 // Every stage is one persistent launch that walks its work list of
 // (frame, block) items; the blocks of a frame are exactly those of the
 // single-frame call, so each frame's results are bit-identical to it.
 // Only frames below kSmallPixels go through these work lists: there a
 // stage's blocks of many frames fill the GPU where one frame's would not.
 // A larger frame already fills it and runs faster through the single-frame
-// kernels, so the graph launches those for it, on kChains streams forked and
-// joined inside the graph.
+// kernels, so the graph launches those for it, spread over a number of
+// streams forked and joined inside the graph (the tuning table's "chains").
 // Running the plan is one hipGraphLaunch.
 #include <hip/hip_runtime.h>
 
@@ -64,16 +63,35 @@ FrameLayout frame_layout(int w, int h, int nd, int npaths, int p2) {
     return l;
 }
 
-// Looks up "WxHxD": variant in a flat JSON object; -1 when absent.
+// Streams for the large frames inside the graph when the table names none,
+// and the most it may name.  Frames of one stream run one after another;
+// frames on different streams overlap, which fills the compute units that
+// one frame's path pass leaves idle in its tail.
+constexpr int kDefaultChains = 2;
+constexpr int kMaxChains = 8;
+
+// Looks up the integer value of "key" in a flat JSON object; `absent` when
+// the key is missing.
+int table_int(const char* table, const char* key, int absent) {
+    if (!table) return absent;
+    const char* p = strstr(table, key);
+    if (!p) return absent;
+    p = strchr(p + strlen(key), ':');
+    if (!p) return absent;
+    return (int)strtol(p + 1, nullptr, 10);
+}
+
+// "WxHxD": lane-layout variant of the path pass for that frame shape.
 int tuned_variant(const char* table, int w, int h, int nd) {
-    if (!table) return -1;
     char key[64];
     snprintf(key, sizeof(key), "\"%dx%dx%d\"", w, h, nd);
-    const char* p = strstr(table, key);
-    if (!p) return -1;
-    p = strchr(p + strlen(key), ':');
-    if (!p) return -1;
-    return (int)strtol(p + 1, nullptr, 10);
+    return table_int(table, key, -1);
+}
+
+// "chains": streams inside the graph for the large frames (1..kMaxChains).
+int tuned_chains(const char* table) {
+    const int c = table_int(table, "\"chains\"", kDefaultChains);
+    return std::max(1, std::min(kMaxChains, c));
 }
 
 enum Stage { kCensus, kCost, kPaths, kMerge, kFill, kSelect, kFused, kMedian, kStages };
@@ -93,10 +111,6 @@ int stage_blocks(Stage st, const Frame& f) {
     }
 }
 
-// Streams for the large frames inside the graph.  Frames in flight on 2-4
-// streams measured up to 3 % slower than one stream on the 64-pair mix once
-// the selection stopped being bandwidth-bound next to the path pass.
-constexpr int kChains = 1;
 constexpr long kSmallPixels = 100000;
 
 bool small_frame(const Frame& f) { return (long)f.width * f.height < kSmallPixels; }
@@ -316,7 +330,8 @@ int32_t sgm_batch_plan_create(const sgm_pair* pairs, int32_t n, const sgm_params
         if (!small_frame(frames[i])) large.push_back(i);
     auto vol = [&](int i) { return (double)frames[i].width * frames[i].height * frames[i].ndisp; };
     std::stable_sort(large.begin(), large.end(), [&](int a, int b) { return vol(a) > vol(b); });
-    const int nchains = std::max(1, std::min<int>(kChains, (int)large.size() + (launches.empty() ? 0 : 1)));
+    const int nchains =
+        std::max(1, std::min<int>(tuned_chains(tune_table), (int)large.size() + (launches.empty() ? 0 : 1)));
     std::vector<std::vector<int>> chain_frames(nchains);
     std::vector<double> load(nchains, 0.0);
     if (!launches.empty()) {

@@ -1,10 +1,15 @@
-"""Autotuner for the batched form: picks, per frame shape (W, H, D), the
-path-kernel lane-layout variant that runs fastest on this GPU, and returns
-the JSON table that sgm_batch_plan_create takes.
+"""Autotuner for the batched form, in two stages, both written into the JSON
+table that sgm_batch_plan_create takes:
 
-Every variant computes identical results (the batch tests check that), so
-tuning only changes speed.  Candidates are timed as one-frame batch plans
-with HIP events on the current stream.
+* per frame shape (W, H, D): the path-kernel lane-layout variant that runs
+  fastest, each candidate timed as a one-frame batch plan;
+* per batch: "chains", the number of streams inside the graph over which
+  the frames of 100k pixels and more are spread (frames on different streams
+  overlap, which fills the compute units that one frame's path pass leaves
+  idle in its tail), each candidate timed as the whole batch plan.
+
+Every choice computes identical results (the batch tests check that), so
+tuning only changes speed.  Timing uses HIP events on the current stream.
 
     python -m paper_2106_07927_amd.tune 1242x375x128 1920x1080x256 ...
 """
@@ -54,6 +59,34 @@ def tune(shapes, params: sgm.Params, device="cuda", reps=5, seed=7):
         table[key] = int(np.argmin(ms))
         timings[key] = [round(t, 4) for t in ms]
     return table, timings
+
+
+def time_plan(lefts, rights, ndisps, params, table: dict, reps=3) -> float:
+    """Milliseconds per run of the whole batch under `table`."""
+    plan = sgm.BatchPlan(lefts, rights, ndisps, params, tune_table=json.dumps(table))
+    try:
+        plan.run()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            plan.run()
+        end.record()
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / reps
+    finally:
+        plan.close()
+
+
+def tune_chains(lefts, rights, ndisps, params: sgm.Params, table: dict, choices=(1, 2, 3, 4),
+                reps=3):
+    """Adds the fastest "chains" for this batch to a copy of `table`; returns
+    (table, {chains: ms})."""
+    ms = {c: round(time_plan(lefts, rights, ndisps, params, {**table, "chains": c}, reps), 4)
+          for c in choices}
+    best = min(ms, key=ms.get)
+    return {**table, "chains": int(best)}, ms
 
 
 def main(argv):
