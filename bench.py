@@ -56,7 +56,7 @@ def parse():
                     help="timed replays of the 64-pair batch (0 skips the batched form)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served trace (0 skips the served form)")
-    ap.add_argument("--serve-short-seconds", type=float, default=15.0,
+    ap.add_argument("--serve-short-seconds", type=float, default=10.0,
                     help="length of the tight-budget and overload traces")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--max-streams", type=int, default=4,
@@ -529,9 +529,12 @@ def served_form(args, torch, sgm, datagen):
     del tight_backend
     torch.cuda.empty_cache()
     # over-load: twice the rate
-    fast = serve.make_trace(specs, 60.0, args.serve_short_seconds, 2, seed=2111)
-    over_mix = run(fast)
-    over_fifo = fifo(fast)
+    # above the load: 2x and 3x the rate, each trace served both ways
+    overload = {}
+    for mult in (2, 3):
+        fast = serve.make_trace(specs, 30.0 * mult, args.serve_short_seconds, 2, seed=2110 + mult)
+        overload[f"{30 * mult}hz_{args.serve_short_seconds:g}s"] = {"continuous": run(fast),
+                                                                     "plain_fifo": fifo(fast)}
     offered = sum(s.width * s.height * s.ndisp for s in specs) * 30.0 / 1e6
     return {"streams": len(specs), "rate_hz": 30.0, "seconds": args.serve_seconds,
             "offered_mdes": round(offered, 1), "arena_gib": round(backend.arena.capacity / 2 ** 30, 2),
@@ -541,8 +544,7 @@ def served_form(args, torch, sgm, datagen):
             "continuous": mix,
             f"first_{args.serve_short_seconds:g}s": {"continuous": prefix_mix, "plain_fifo": plain},
             f"tight_arena_{int(tight_gib)}gib_{args.serve_short_seconds:g}s": tight,
-            f"overload_60hz_{args.serve_short_seconds:g}s": {"continuous": over_mix,
-                                                            "plain_fifo": over_fifo},
+            "overload": overload,
             "frame_ms_by_shape": {f"{w}x{h}x{d}": round(v, 4) for (w, h, d), v in frame_ms.items()}}
 
 

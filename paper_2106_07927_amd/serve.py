@@ -370,11 +370,13 @@ class FakeBackend:
 
 class GpuBackend:
     """Slots are StereoSGM buffer sets, with their own device inputs, carved
-    out of one device arena; frames run on a pool of HIP streams (default
-    priority)."""
+    out of one device arena; frames run on a fixed pool of HIP streams
+    (default priority).  Everything a slot needs besides its arena range --
+    its stream and its pinned output buffer -- is made once, up front, and
+    reused, so admitting a slot (also after an eviction) allocates nothing."""
 
     def __init__(self, specs, params, frames_per_stream: int = 4, device="cuda", occlusion=0.05,
-                 arena_bytes: int = 8 << 30):
+                 arena_bytes: int = 8 << 30, hip_streams: int = 8, slots_per_stream: int = 2):
         import torch
 
         from . import sgm
@@ -394,6 +396,11 @@ class GpuBackend:
         self.memory = torch.empty(self.arena.capacity + Arena.ALIGN, dtype=torch.uint8,
                                   device=self.device)
         self.base = (-self.memory.data_ptr()) % Arena.ALIGN
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(hip_streams)]
+        self._next_stream = 0
+        # pinned host buffers for D, per stream spec, one per possible slot
+        self.out_pool = [[torch.empty((sp.height, sp.width), dtype=torch.uint16).pin_memory()
+                          for _ in range(slots_per_stream)] for sp in specs]
         self.result_of = {}
         self.t0_event = None
         self.t0 = 0.0
@@ -416,6 +423,8 @@ class GpuBackend:
         in one free range."""
         torch, sgm = self.torch, self.sgm
         sp = self.specs[s]
+        if not self.out_pool[s]:
+            return None
         off = self.arena.alloc(self.sizes[s])
         if off is None:
             return None
@@ -433,13 +442,15 @@ class GpuBackend:
         eng = sgm.StereoSGM(sp.width, sp.height, prm, device=self.device, alloc=take)
         assert cursor[0] - self.base - off <= self.sizes[s], "slot layout exceeds slot_bytes"
         return {"eng": eng, "left": left, "right": right, "off": off, "stream_index": s,
-                "out": torch.empty((sp.height, sp.width), dtype=torch.uint16).pin_memory(),
-                "stream": torch.cuda.Stream(device=self.device)}
+                "out": self.out_pool[s].pop()}
 
     def submit(self, s, slot, req, keep):
         torch = self.torch
         hl, hr = self.pool[s][req.frame]
-        st = slot["stream"]
+        # streams in turn: with fewer frames in flight than streams, two
+        # frames in flight never share one
+        st = self.streams[self._next_stream % len(self.streams)]
+        self._next_stream += 1
         with torch.cuda.stream(st):
             slot["left"].copy_(hl, non_blocking=True)
             slot["right"].copy_(hr, non_blocking=True)
@@ -461,6 +472,7 @@ class GpuBackend:
     def free_slot(self, handle):
         # only idle slots are released: their last frame has completed
         self.arena.release(handle["off"], self.sizes[handle["stream_index"]])
+        self.out_pool[handle["stream_index"]].append(handle["out"])
         handle.clear()
 
     def idle(self, next_arrival=None):
