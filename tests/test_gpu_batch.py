@@ -190,4 +190,18 @@ def test_batch_mixed_workload_matches_plain_and_oracle(torch_dev):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(plan.disp[i].cpu().numpy(), eng.disp.cpu().numpy(),
                                       err_msg=f"pair {i} {key}")
+    first = [d.cpu().numpy() for d in plan.disp]
     plan.close()
+    # the number of streams inside the graph (tuning table "chains") never
+    # changes results
+    import json
+    for chains in (1, 3):
+        say(f"64-pair mixed batch, {chains} stream(s) inside the graph")
+        other = sgm.BatchPlan(lefts, rights, [s[2] for s in specs], prm,
+                              tune_table=json.dumps({"chains": chains}))
+        other.run()
+        torch.cuda.synchronize()
+        for i in range(len(specs)):
+            np.testing.assert_array_equal(other.disp[i].cpu().numpy(), first[i],
+                                          err_msg=f"pair {i}, chains {chains}")
+        other.close()
