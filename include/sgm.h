@@ -132,8 +132,9 @@ int32_t sgm_cost_ncc(const uint8_t* left, const uint8_t* right, int32_t width, i
  *              so that every S_bar fits uint16 exactly
  *   agg_out    uint16 [height][width][ndisp], 16-byte aligned
  *   work       device scratch of at least sgm_aggregate_work_bytes(...) bytes,
- *              16-byte aligned, holding one slice per path between the path
- *              pass and the sum; contents on return are unspecified
+ *              16-byte aligned, holding one slice per pair of opposite path
+ *              directions between the path pass and the sum; contents on
+ *              return are unspecified
  * Errors: SGM_ERR_ARG (sizes, width*height*ndisp > SGM_MAX_VOLUME, npaths
  *         not 4/8, p1 > p2, overflow bound), SGM_ERR_WORKSPACE (work NULL or
  *         work_bytes too small), SGM_ERR_ALIGN.
@@ -143,9 +144,10 @@ int32_t sgm_aggregate(const uint8_t* cost, int32_t width, int32_t height,
                       uint16_t* agg_out, void* work, size_t work_bytes,
                       void* stream);
 
-/* Bytes of `work` that sgm_aggregate needs: npaths slices of
+/* Bytes of `work` that sgm_aggregate needs: npaths / 2 slices of
  * width*height*ndisp elements (rounded up to 256), 1 byte each when
- * p2 <= 255, else 2.  0 on invalid sizes or penalties. */
+ * p2 <= 127 (a pair's two penalty parts sum to at most 254), else 2.
+ * 0 on invalid sizes or penalties. */
 size_t sgm_aggregate_work_bytes(int32_t width, int32_t height, int32_t ndisp,
                                 int32_t npaths, int32_t p2);
 
@@ -183,7 +185,7 @@ size_t sgm_wta_lrc_work_elems(int32_t width, int32_t height);
  * speed-up for GPU SGM (Sec. 4.2); here the path sum of Eq. (sgm_path_aggr)
  * is formed on chip inside the selection pass.  disp_out and disp_right_out
  * are bit-identical to those two calls with the same arguments.
- * The fused form applies when ndisp % 16 == 0 and p2 <= 255; other valid
+ * The fused form applies when ndisp % 16 == 0 (any legal p2); other valid
  * arguments run the two unfused calls on the same workspace.
  *   cost, npaths, p1, p2          as for sgm_aggregate
  *   lr_tolerance, median3x3,
