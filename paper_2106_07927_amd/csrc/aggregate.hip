@@ -149,7 +149,8 @@ PathLayout path_layout(int ndisp, int variant) {
 // horizontal lines to trade per-step latency for fewer instructions.
 int default_variant(int width, int height, int ndisp) {
     const long px = (long)width * height;
-    if (ndisp <= 32 || ndisp > 128) return 0;
+    if (ndisp <= 32) return 0;
+    if (ndisp > 128) return px >= 400000 ? 1 : 0;    // 1242x375, 1920x1080 at D = 256
     if (px >= 1500000) return 1;
     if (ndisp > 64 && px >= 400000) return 2;
     return 0;
