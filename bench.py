@@ -296,7 +296,20 @@ def other_config(args, torch, sgm, datagen, dev, name, digest):
            "step_ms_p50": round(percentile(per_step, 0.5), 5),
            "step_ms_p99": round(percentile(per_step, 0.99), 5),
            "roofline": fr.roofline(stages["aggregate_select"])}
-    del eng
+    # the same frame with 4 frames in flight (engines and streams in turn)
+    engs = [eng] + [fr.engine() for _ in range(3)]
+    side = [torch.cuda.Stream(device=dev) for _ in range(4)]
+    for i in range(8):
+        engs[i % 4].run(fr.left, fr.right, stream=side[i % 4])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        engs[i % 4].run(fr.left, fr.right, stream=side[i % 4])
+    torch.cuda.synchronize()
+    ms4 = (time.perf_counter() - t0) * 1e3 / steps
+    out["in_flight_4"] = {"ms_per_frame": round(ms4, 5), "value": round(fr.des / (ms4 * 1e-3) / 1e6, 1),
+                          "fps": round(1000.0 / ms4, 1)}
+    del eng, engs
     torch.cuda.empty_cache()
     return out
 

@@ -9,13 +9,17 @@ simulated camera streams on one GPU.
   allocated once: the budget is the memory the server holds, not a count.
   When a stream needs a slot that does not fit, idle slots of other streams
   are released back to the arena (least recently used first) -- no device
-  allocation or free happens while serving.  A frame is
-  admitted as soon as one of its stream's slots is idle (or a new one fits
-  the budget) and a HIP stream of the pool is free,
-  so frames that arrive while others run start at once and overlap with them
-  on the device.  Per stream, frames are admitted in arrival order.
-* Per frame: pinned H2D copy of the pair, the four ABI calls, D2H copy of
-  the disparity map, all on the slot's HIP stream; completion is an event.
+  allocation or free happens while serving.  HIP streams and the pinned
+  output buffers are made once, so admitting a slot allocates nothing at
+  all.  A frame is admitted as soon as one of its stream's slots is idle
+  (or a new one fits the budget) and fewer than `hip_streams` frames are in
+  flight, so frames that arrive while others run start at once and overlap
+  with them on the device.  Per stream, frames are admitted in arrival
+  order.  A run hands its slots back to the arena at the end.
+* Per frame: pinned H2D copy of the pair, the streamlined path (census of
+  both images, cost, aggregation fused with the selection), D2H copy of the
+  disparity map, all on one HIP stream of the pool, taken in turn;
+  completion is an event.
   Latency = time of the event (read against an event recorded at the start)
   minus the arrival time.
 * The plain reference serves the same trace FIFO, one frame at a time on one
