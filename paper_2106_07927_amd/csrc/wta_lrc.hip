@@ -3,8 +3,10 @@
 // the left-right consistency check (Eq. LR_check) and the 3x3 median
 // (Sec. 2.1.3, Sec. 2.2.4), gfx950.
 //
-// Pass 1 (select_kernel): one wave walks a segment of one row, one pixel per
-// step, reading that pixel's S_bar vector once and coalesced (lane j holds
+// Pass 1, D a multiple of 16: the tile pass of the fused selection
+// (select_fused_kernel, below), fed S_bar itself as its one uint16 slice.
+// Pass 1, other D (select_kernel): one wave walks a segment of one row, one
+// pixel per step, reading that pixel's S_bar vector once and coalesced (lane j holds
 // disparities j*EPL .. j*EPL+EPL-1); loads run a chunk of pixels ahead.
 // Every value becomes a 32-bit key (S_bar << 8) | d, so a plain minimum
 // yields the smallest cost and, among equal costs, the smallest d.
@@ -743,7 +745,17 @@ hipError_t launch_wta_lrc(const Frame& f, hipStream_t stream) {
     fill_keys_kernel<<<fill_blocks(n), 256, 0, stream>>>(f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    launch_select_any<false>(&f, nullptr, f.ndisp, stream);
+    if (f.ndisp % 16 == 0) {
+        // the fused selection's tile pass, fed S_bar itself as its one
+        // uint16 "slice" (the sum of one slice is the slice): S_bar is read
+        // once, in 16-byte blocks, instead of by the row-segment pass
+        Frame g = f;
+        g.slices = reinterpret_cast<uint8_t*>(f.agg);
+        g.slice_stride = 0;
+        launch_fused_t<1, false, false>(&g, nullptr, f.ndisp, stream);
+    } else {
+        launch_select_any<false>(&f, nullptr, f.ndisp, stream);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 g2(median_blocks_x(f.width), (f.height + kTH - 1) / kTH);
