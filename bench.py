@@ -77,7 +77,7 @@ def parse():
 # 2.4 GHz and the kernels' durations).  An entry holds only for the kernel
 # sources whose digest it names; otherwise the figures are null.
 COUNTERS = {
-    "sgm_aggregate_select": {"sources": "0442fcebf60a1f4a", "traffic": 1475.5, "valu_busy": 0.605},
+    "sgm_aggregate_select": {"sources": "c1533febf63fe57b", "traffic": 1475.5, "valu_busy": 0.602},
 }
 
 KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "paths.hip", "wta_lrc.hip",

@@ -31,6 +31,7 @@ GPU, FakeBackend simulates service times on a virtual clock for CPU tests.
 from __future__ import annotations
 
 import collections
+import gc
 import math
 import time
 from dataclasses import dataclass, field
@@ -241,16 +242,37 @@ class Server:
         """Serves the trace; `keep(request)` says whether to copy a result to
         the host for checking (the backend keeps it in result_of).  With
         `release` the slots go back to the backend at the end, so that
-        another server can use its memory; else they stay for the next run."""
+        another server can use its memory; else they stay for the next run.
+        Before the clock starts, every stream of the trace that has no slot
+        gets one while the budget holds them without evictions (streams are
+        known up front), and Python's garbage collector is paused for the
+        run so that no collection lands inside a frame's latency."""
         stats = Stats()
         for s, size in enumerate(self.sizes):
             if size > self.budget:
                 stats.rejected += sum(1 for r in trace if r.stream == s)
         trace = [r for r in trace if self.sizes[r.stream] <= self.budget]
+        for s in dict.fromkeys(r.stream for r in trace):
+            if not self.slots[s] and self.used_bytes + self.sizes[s] <= self.budget:
+                handle = self.backend.alloc_slot(s)
+                if handle is None:
+                    continue
+                self.slots[s].append({"id": 0, "handle": handle, "job": None, "last": self._tick})
+                self.used_bytes += self.sizes[s]
         pending = collections.defaultdict(collections.deque)
         inflight = []
         waited = set()
         i = 0
+        gc_enabled = gc.isenabled()
+        gc.collect()
+        gc.disable()
+        try:
+            return self._serve(trace, keep, release, stats, pending, inflight, waited, i)
+        finally:
+            if gc_enabled:
+                gc.enable()
+
+    def _serve(self, trace, keep, release, stats, pending, inflight, waited, i) -> Stats:
         self.backend.start()
         while i < len(trace) or inflight or any(pending.values()):
             now = self.backend.now()
