@@ -155,6 +155,22 @@ def test_wta_lrc_parity(dev, w, h, nd, t, med):
     np.testing.assert_array_equal(host(d), ref)
 
 
+@pytest.mark.parametrize("w,h,nd", [(96, 3, 32), (70, 4, 48), (33, 2, 30)])
+def test_wta_lrc_values_near_uint16_max(dev, w, h, nd):
+    """S_bar values at the top of the uint16 range (the tile pass for
+    D % 16 == 0 and the row-segment pass otherwise), with ties."""
+    from paper_2106_07927_amd import sgm
+    say(f"wta_lrc near 65535, {w}x{h} D{nd}")
+    rng = np.random.default_rng(7 * w + nd)
+    agg = (65535 - rng.integers(0, 6, (h, w, nd))).astype(np.uint16)
+    d, dr = sgm.sgm_wta_lrc(to_dev(agg, dev), 1, True, want_right=True)
+    dl_ref = oracle.wta(agg)
+    dr_ref = oracle.right_disparity(agg)
+    ref = oracle.median3x3(oracle.lr_check(dl_ref, dr_ref, 1))
+    np.testing.assert_array_equal(host(dr), dr_ref)
+    np.testing.assert_array_equal(host(d), ref)
+
+
 # ------------------------------------------------------------ pipelines ---
 def _params(cfg):
     return oracle.Params(win_w=cfg["win_w"], win_h=cfg["win_h"], ndisp=cfg["ndisp"],
