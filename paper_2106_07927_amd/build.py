@@ -5,8 +5,9 @@
 Every source is compiled by hipcc for gfx950 only, in-tree, into
 ``paper_2106_07927_amd/libsgm.so``.  Packed-FP32 instruction selection is
 switched off for the device code.  ``paths.hip`` (the path pass) is compiled
-once per lane layout (-DSGM_PATH_LAYOUT=k), so its kernels build in
-parallel.
+once per lane layout (-DSGM_PATH_LAYOUT=k) and per form (-DSGM_PATH_PART=0
+for the single-frame kernels, 1 for the work-list kernels), so its kernels
+build in parallel.
 """
 from __future__ import annotations
 
@@ -28,7 +29,8 @@ CPP_SOURCES = ["sgm_capi.cpp", "batch.cpp"]
 PATH_LAYOUTS = 12          # entries of kPathLayouts in sgm_internal.h
 # (source, object, extra flags) of every translation unit
 UNITS = ([(s, s + ".o", []) for s in HIP_SOURCES + CPP_SOURCES] +
-         [("paths.hip", f"paths_{k}.hip.o", [f"-DSGM_PATH_LAYOUT={k}"]) for k in range(PATH_LAYOUTS)])
+         [("paths.hip", f"paths_{k}_{part}.hip.o", [f"-DSGM_PATH_LAYOUT={k}", f"-DSGM_PATH_PART={part}"])
+          for k in range(PATH_LAYOUTS) for part in (0, 1)])
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I", INCLUDE, "-I", CSRC]
@@ -90,6 +92,8 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     out of date) and link libsgm.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     todo = [u for u in UNITS if not incremental or _stale(u)]
+    # the path-pass objects take longest: start them first
+    todo.sort(key=lambda u: 0 if u[0] == "paths.hip" else 1)
     workers = max(1, min(len(todo), os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(max_workers=workers) as pool:
         list(pool.map(_compile, todo))

@@ -102,7 +102,8 @@ hipError_t launch_paths_any(const Frame* one, const WorkList* wl, int ndisp, int
 #define SGM_CASE(K)                                                                                  \
     if (l.nreg_h == kPathLayouts[K].nreg_h && l.lpl_h == kPathLayouts[K].lpl_h &&                   \
         l.nreg_o == kPathLayouts[K].nreg_o && l.lpl_o == kPathLayouts[K].lpl_o)                     \
-        return launch_paths_layout_id<K>(one, wl, ndisp, u8, nblocks, stream);
+        return one ? launch_paths_layout_id<K>(*one, ndisp, u8, nblocks, stream)                     \
+                   : launch_paths_batch_layout_id<K>(*wl, ndisp, u8, nblocks, stream);
     SGM_CASE(0)
     SGM_CASE(1)
     SGM_CASE(2)

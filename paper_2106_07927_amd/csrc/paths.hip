@@ -2,7 +2,8 @@
 // of Ruf et al. 2021 (Sec. 2.1.2), gfx950.
 //
 // This file is compiled once per lane layout (-DSGM_PATH_LAYOUT=<index into
-// kPathLayouts>), so the layouts' kernels build in parallel; aggregate.hip
+// kPathLayouts>) and per form (-DSGM_PATH_PART=0: the single-frame kernel,
+// 1: the work-list kernel), so the kernels build in parallel; aggregate.hip
 // holds the pass that sums the slices and picks the layout.
 //
 // Lines.  Every path direction r splits the image into independent lines:
@@ -643,25 +644,25 @@ __global__ __launch_bounds__(kThreads) void paths_batch_kernel(WorkList wl) {
     }
 }
 
-// Path-kernel launch for one lane layout; `batch` selects the persistent
-// work-list form.
+// Path-kernel launches for one lane layout: the single-frame kernel, or the
+// persistent work-list form.  The two are compiled in separate objects
+// (SGM_PATH_PART 0 and 1), so the library's longest compile splits in two.
+struct LayoutFlags {
+    bool alh, alo, padded;
+};
+
+__host__ inline LayoutFlags layout_flags(int nh, int lh, int no, int lo, int ndisp) {
+    return {ndisp % (2 * nh) == 0, ndisp % (2 * no) == 0, lh * 2 * nh > ndisp || lo * 2 * no > ndisp};
+}
+
+#if SGM_PATH_PART == 0
 template <int NH, int LH, int NO, int LO>
-hipError_t launch_paths_layout(const Frame* one, const WorkList* wl, int ndisp, bool u8,
-                               int nblocks, hipStream_t stream) {
-    const bool alh = ndisp % (2 * NH) == 0;
-    const bool alo = ndisp % (2 * NO) == 0;
-    const bool pdh = LH * 2 * NH > ndisp;
-    const bool pdo = LO * 2 * NO > ndisp;
-    // an ordered item list is dispatched one block per item, so the hardware
-    // hands out the longest lines first
-    const int grid = (one || wl->items) ? nblocks : persistent_grid(nblocks);
-#define SGM_PATHS(A, B, C, D, U)                                                                   \
-    do {                                                                                           \
-        if (one) paths_kernel<NH, LH, NO, LO, A, B, C, D, U><<<grid, kThreads, 0, stream>>>(*one); \
-        else paths_batch_kernel<NH, LH, NO, LO, A, B, C, D, U><<<grid, kThreads, 0, stream>>>(*wl); \
-    } while (0)
-    if (alh && alo) {
-        if (!pdh && !pdo) {
+hipError_t launch_paths_single(const Frame& one, int ndisp, bool u8, int nblocks, hipStream_t stream) {
+    const LayoutFlags fl = layout_flags(NH, LH, NO, LO, ndisp);
+#define SGM_PATHS(A, B, C, D, U) \
+    paths_kernel<NH, LH, NO, LO, A, B, C, D, U><<<nblocks, kThreads, 0, stream>>>(one)
+    if (fl.alh && fl.alo) {
+        if (!fl.padded) {
             if (u8) SGM_PATHS(true, false, true, false, true);
             else SGM_PATHS(true, false, true, false, false);
         } else {
@@ -675,18 +676,55 @@ hipError_t launch_paths_layout(const Frame* one, const WorkList* wl, int ndisp, 
 #undef SGM_PATHS
     return hipGetLastError();
 }
+#else
+template <int NH, int LH, int NO, int LO>
+hipError_t launch_paths_worklist(const WorkList& wl, int ndisp, bool u8, int nblocks, hipStream_t stream) {
+    const LayoutFlags fl = layout_flags(NH, LH, NO, LO, ndisp);
+    // an ordered item list is dispatched one block per item, so the hardware
+    // hands out the longest lines first
+    const int grid = wl.items ? nblocks : persistent_grid(nblocks);
+#define SGM_PATHS(A, B, C, D, U) \
+    paths_batch_kernel<NH, LH, NO, LO, A, B, C, D, U><<<grid, kThreads, 0, stream>>>(wl)
+    if (fl.alh && fl.alo) {
+        if (!fl.padded) {
+            if (u8) SGM_PATHS(true, false, true, false, true);
+            else SGM_PATHS(true, false, true, false, false);
+        } else {
+            if (u8) SGM_PATHS(true, true, true, true, true);
+            else SGM_PATHS(true, true, true, true, false);
+        }
+    } else {
+        if (u8) SGM_PATHS(false, true, false, true, true);
+        else SGM_PATHS(false, true, false, true, false);
+    }
+#undef SGM_PATHS
+    return hipGetLastError();
+}
+#endif
 
 }  // namespace
 
 #ifndef SGM_PATH_LAYOUT
 #error "paths.hip is compiled once per lane layout: -DSGM_PATH_LAYOUT=<index>"
 #endif
+#if !defined(SGM_PATH_PART) || (SGM_PATH_PART != 0 && SGM_PATH_PART != 1)
+#error "paths.hip is compiled in two parts: -DSGM_PATH_PART=0 (single frame) or 1 (work list)"
+#endif
 
+#if SGM_PATH_PART == 0
 template <>
-hipError_t launch_paths_layout_id<SGM_PATH_LAYOUT>(const Frame* one, const WorkList* wl, int ndisp,
-                                                   bool u8, int nblocks, hipStream_t stream) {
+hipError_t launch_paths_layout_id<SGM_PATH_LAYOUT>(const Frame& one, int ndisp, bool u8, int nblocks,
+                                                   hipStream_t stream) {
     constexpr PathLayout L = kPathLayouts[SGM_PATH_LAYOUT];
-    return launch_paths_layout<L.nreg_h, L.lpl_h, L.nreg_o, L.lpl_o>(one, wl, ndisp, u8, nblocks, stream);
+    return launch_paths_single<L.nreg_h, L.lpl_h, L.nreg_o, L.lpl_o>(one, ndisp, u8, nblocks, stream);
 }
+#else
+template <>
+hipError_t launch_paths_batch_layout_id<SGM_PATH_LAYOUT>(const WorkList& wl, int ndisp, bool u8,
+                                                         int nblocks, hipStream_t stream) {
+    constexpr PathLayout L = kPathLayouts[SGM_PATH_LAYOUT];
+    return launch_paths_worklist<L.nreg_h, L.lpl_h, L.nreg_o, L.lpl_o>(wl, ndisp, u8, nblocks, stream);
+}
+#endif
 
 }  // namespace sgm

@@ -265,14 +265,19 @@ constexpr PathLayout kPathLayouts[kNumPathLayouts] = {
     {2, 16, 4, 8}, {1, 64, 4, 16}, {2, 32, 4, 16}, {1, 64, 8, 8}, {2, 64, 8, 16}, {4, 32, 8, 16},
 };
 
-// The path pass for layout kPathLayouts[ID] (one object per layout): the
-// single-frame kernel when `one` is set, else the work-list kernel.
+// The path pass for layout kPathLayouts[ID] (paths.hip compiled per layout,
+// in two objects): the single-frame kernel for one frame, or the work-list
+// kernel for a batch.
 template <int ID>
-hipError_t launch_paths_layout_id(const Frame* one, const WorkList* wl, int ndisp, bool u8,
-                                  int nblocks, hipStream_t stream);
-#define SGM_DECLARE_PATH_LAYOUT(K)                                                             \
-    template <>                                                                                \
-    hipError_t launch_paths_layout_id<K>(const Frame*, const WorkList*, int, bool, int, hipStream_t);
+hipError_t launch_paths_layout_id(const Frame& one, int ndisp, bool u8, int nblocks, hipStream_t stream);
+template <int ID>
+hipError_t launch_paths_batch_layout_id(const WorkList& wl, int ndisp, bool u8, int nblocks,
+                                        hipStream_t stream);
+#define SGM_DECLARE_PATH_LAYOUT(K)                                                              \
+    template <>                                                                                 \
+    hipError_t launch_paths_layout_id<K>(const Frame&, int, bool, int, hipStream_t);            \
+    template <>                                                                                 \
+    hipError_t launch_paths_batch_layout_id<K>(const WorkList&, int, bool, int, hipStream_t);
 SGM_DECLARE_PATH_LAYOUT(0)
 SGM_DECLARE_PATH_LAYOUT(1)
 SGM_DECLARE_PATH_LAYOUT(2)
