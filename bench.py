@@ -77,7 +77,7 @@ def parse():
 # 2.4 GHz and the kernels' durations).  An entry holds only for the kernel
 # sources whose digest it names; otherwise the figures are null.
 COUNTERS = {
-    "sgm_aggregate_select": {"sources": "c1533febf63fe57b", "traffic": 1475.5, "valu_busy": 0.602},
+    "sgm_aggregate_select": {"sources": "fd2e8cc8a42debe9", "traffic": 1475.4, "valu_busy": 0.604},
 }
 
 KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "paths.hip", "wta_lrc.hip",
