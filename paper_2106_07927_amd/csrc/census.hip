@@ -45,12 +45,33 @@ __device__ __forceinline__ void census_tile(CensusTile<RX, RY>& t, const uint8_t
     using T = CensusTile<RX, RY>;
     const int x0 = bx * kCensusTileW;
     const int y0 = by * kCensusTileH;
-    for (int i = threadIdx.x; i < T::LW * T::LH; i += kThreads) {
+    // Every load of the tile is issued before the first LDS write, so staging
+    // costs one memory round trip: each position reads the clamped pixel
+    // (always inside the image), and a tile that reaches past the border
+    // then overwrites those positions with the zero margin.
+    constexpr int kN = T::LW * T::LH;
+    constexpr int kIt = (kN + kThreads - 1) / kThreads;
+    uint32_t v[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = min((int)threadIdx.x + it * kThreads, kN - 1);
         const int ly = i / T::LW, lx = i - ly * T::LW;
-        const int gx = x0 + lx - RX, gy = y0 + ly - RY;
-        uint8_t v = 0;
-        if (gx >= 0 && gx < width && gy >= 0 && gy < height) v = img[(size_t)gy * pitch + gx];
-        t.px[ly * T::LWP + lx] = v;
+        const int cx = min(max(x0 + lx - RX, 0), width - 1), cy = min(max(y0 + ly - RY, 0), height - 1);
+        v[it] = img[(size_t)cy * pitch + cx];
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = min((int)threadIdx.x + it * kThreads, kN - 1);   // equal values where clamped
+        const int ly = i / T::LW, lx = i - ly * T::LW;
+        t.px[ly * T::LWP + lx] = (uint8_t)v[it];
+    }
+    if (x0 < RX || y0 < RY || x0 + T::LW - RX > width || y0 + T::LH - RY > height) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kN; i += kThreads) {
+            const int ly = i / T::LW, lx = i - ly * T::LW;
+            const int gx = x0 + lx - RX, gy = y0 + ly - RY;
+            if (gx < 0 || gx >= width || gy < 0 || gy >= height) t.px[ly * T::LWP + lx] = 0;
+        }
     }
     __syncthreads();
 

@@ -28,10 +28,27 @@ __device__ __forceinline__ int stage_row(CostTile& t, const uint64_t* __restrict
     const uint64_t* rowl = cl + (size_t)y * width;
     const uint64_t* rowr = cr + (size_t)y * width;
     const int rbase = x0 - (ndisp - 1);
-    for (int i = threadIdx.x; i < npix; i += blockDim.x) t.sl[i] = rowl[x0 + i];
-    for (int i = threadIdx.x; i < npix + ndisp - 1; i += blockDim.x) {
-        const int x = rbase + i;
-        t.sr[i] = (x >= 0) ? rowr[x] : 0ull;
+    // entries [0, npix) of the left row, then [0, npix + D - 1) of the right
+    // one; all loads are issued before the first LDS write (one round trip)
+    const int nl = npix, n = npix + npix + ndisp - 1;
+    constexpr int kIt = (kCostPix + kCostPix + kMaxD - 1 + 127) / 128;   // blocks of >= 128 threads
+    uint64_t v[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = (int)threadIdx.x + it * (int)blockDim.x;
+        v[it] = 0ull;
+        if (i < nl) {
+            v[it] = rowl[x0 + i];
+        } else if (i < n) {
+            const int x = rbase + (i - nl);
+            if (x >= 0) v[it] = rowr[x];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = (int)threadIdx.x + it * (int)blockDim.x;
+        if (i < nl) t.sl[i] = v[it];
+        else if (i < n) t.sr[i - nl] = v[it];
     }
     __syncthreads();
     return npix;
@@ -40,34 +57,34 @@ __device__ __forceinline__ int stage_row(CostTile& t, const uint64_t* __restrict
 // D a multiple of 4.  Thread (q, g) produces disparities 4q .. 4q+3 for the
 // PPG consecutive pixels of group g; the right descriptors it needs,
 // CR(x - d) for those pixels and disparities, are PPG + 3 consecutive LDS
-// entries, read once into registers and reused across the run.
-template <int PPG>
-__device__ __forceinline__ void cost_run_vec4(CostTile& t, const uint64_t* __restrict__ cl,
-                                              const uint64_t* __restrict__ cr, int width,
-                                              int ndisp, uint8_t* __restrict__ cost, int bx, int y) {
-    const int x0 = bx * kCostPix;
-    const int npix = stage_row(t, cl, cr, width, ndisp, x0, y);
+// entries, read once into registers and reused across the run.  FULL: the
+// run holds kCostPix pixels and starts at x0 >= D - 1, so no pixel lies past
+// the row's end and no disparity reaches left of the image (no checks).
+template <int PPG, bool FULL>
+__device__ __forceinline__ void cost_tile_vec4(const CostTile& t, int npix, int ndisp,
+                                               uint32_t* __restrict__ out, int x0) {
     const int dwords = ndisp >> 2;                 // dwords per pixel
     const int q = threadIdx.x % dwords;
     const int g = threadIdx.x / dwords;
     const int d0 = q * 4;
     const int p0 = g * PPG;
-    if (p0 < npix) {
-        // sr index of CR(x - d) for pixel p: p + ndisp - 1 - d
-        const int rb = p0 + ndisp - 1 - d0 - 3;
-        uint64_t r[PPG + 3];
+    if (!FULL && p0 >= npix) return;
+    // sr index of CR(x - d) for pixel p: p + ndisp - 1 - d
+    const int rb = p0 + ndisp - 1 - d0 - 3;
+    uint64_t r[PPG + 3];
 #pragma unroll
-        for (int k = 0; k < PPG + 3; ++k) r[k] = (rb + k < npix + ndisp - 1) ? t.sr[rb + k] : 0ull;
-        uint32_t* out = reinterpret_cast<uint32_t*>(cost + ((size_t)y * width + x0) * ndisp);
+    for (int k = 0; k < PPG + 3; ++k) r[k] = (FULL || rb + k < npix + ndisp - 1) ? t.sr[rb + k] : 0ull;
+    uint32_t* o = out + p0 * dwords + q;
 #pragma unroll
-        for (int i = 0; i < PPG; ++i) {
-            const int p = p0 + i;
-            if (p < npix) {
-                const uint64_t l = t.sl[p];
-                uint32_t c0 = __popcll(l ^ r[i + 3]);
-                uint32_t c1 = __popcll(l ^ r[i + 2]);
-                uint32_t c2 = __popcll(l ^ r[i + 1]);
-                uint32_t c3 = __popcll(l ^ r[i]);
+    for (int i = 0; i < PPG; ++i) {
+        const int p = p0 + i;
+        if (FULL || p < npix) {
+            const uint64_t l = t.sl[p];
+            uint32_t c0 = __popcll(l ^ r[i + 3]);
+            uint32_t c1 = __popcll(l ^ r[i + 2]);
+            uint32_t c2 = __popcll(l ^ r[i + 1]);
+            uint32_t c3 = __popcll(l ^ r[i]);
+            if (!FULL) {
                 const int x = x0 + p;
                 if (x < d0 + 3) {                       // some of d0..d0+3 exceed x
                     c0 = (x - d0 >= 0) ? c0 : 255u;
@@ -75,10 +92,22 @@ __device__ __forceinline__ void cost_run_vec4(CostTile& t, const uint64_t* __res
                     c2 = (x - d0 - 2 >= 0) ? c2 : 255u;
                     c3 = (x - d0 - 3 >= 0) ? c3 : 255u;
                 }
-                out[p * dwords + q] = c0 | (c1 << 8) | (c2 << 16) | (c3 << 24);
             }
+            // bytes c0..c3 (each <= 255): two shift-ors and one byte permute
+            o[i * dwords] = __builtin_amdgcn_perm(c2 | (c3 << 8), c0 | (c1 << 8), 0x05040100u);
         }
     }
+}
+
+template <int PPG>
+__device__ __forceinline__ void cost_run_vec4(CostTile& t, const uint64_t* __restrict__ cl,
+                                              const uint64_t* __restrict__ cr, int width,
+                                              int ndisp, uint8_t* __restrict__ cost, int bx, int y) {
+    const int x0 = bx * kCostPix;
+    const int npix = stage_row(t, cl, cr, width, ndisp, x0, y);
+    uint32_t* out = reinterpret_cast<uint32_t*>(cost + ((size_t)y * width + x0) * ndisp);
+    if (npix == kCostPix && x0 >= ndisp - 1) cost_tile_vec4<PPG, true>(t, npix, ndisp, out, x0);
+    else cost_tile_vec4<PPG, false>(t, npix, ndisp, out, x0);
     __syncthreads();   // the tile is reused by the next work item
 }
 
