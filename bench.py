@@ -77,7 +77,7 @@ def parse():
 # 2.4 GHz and the kernels' durations).  An entry holds only for the kernel
 # sources whose digest it names; otherwise the figures are null.
 COUNTERS = {
-    "sgm_aggregate_select": {"sources": "fd2e8cc8a42debe9", "traffic": 1475.4, "valu_busy": 0.604},
+    "sgm_aggregate_select": {"sources": "627a9e995945069a", "traffic": 1474.9, "valu_busy": 0.605},
 }
 
 KERNEL_SOURCES = ("census.hip", "cost.hip", "aggregate.hip", "paths.hip", "wta_lrc.hip",
