@@ -4,8 +4,10 @@ Census: hand-derived descriptors (bit direction, raster order, zero margin,
 window orientation), invariance under strictly increasing grey maps that fix
 0, and shift equivariance.  The paper prints no census example, so the bit
 layout itself rests on the readings listed with the design notes.
-Cost: hand-built XOR/popcount, the 0xFF rule for x - d < 0, and zero cost at
-the true shift of a pure-shift pair.
+Cost: hand-built XOR/popcount, the 0xFF rule for x - d < 0, zero cost at
+the true shift of a pure-shift pair, and census + cost together against a
+count of disagreeing window comparisons taken straight from the images (no
+descriptor formed), which holds for any bit layout of the descriptors.
 """
 import numpy as np
 import pytest
@@ -123,3 +125,44 @@ def test_cost_zero_at_true_shift(oracle_lib, win, d0):
     for d in range(nd):
         assert np.all(c[:, :d, d] == 255)
         assert np.all(c[:, d:, d] <= bits)
+
+
+def _cost_from_images(left, right, win, nd):
+    """Hamming cost written straight from the images: for every window offset,
+    whether the neighbour is darker than the centre in the left image and in
+    the right image at x - d, counted where the two disagree; a zero margin
+    outside the image; 255 where x - d < 0.  No descriptor is formed, so the
+    count does not depend on how the bits of a descriptor are laid out."""
+    h, w = left.shape
+    rx, ry = (win[0] - 1) // 2, (win[1] - 1) // 2
+    pl = np.zeros((h + 2 * ry, w + 2 * rx), np.int64)
+    pr = np.zeros_like(pl)
+    pl[ry:ry + h, rx:rx + w] = left
+    pr[ry:ry + h, rx:rx + w] = right
+    bits_l, bits_r = [], []
+    for dy in range(-ry, ry + 1):
+        for dx in range(-rx, rx + 1):
+            if dx == 0 and dy == 0:
+                continue
+            bits_l.append(pl[ry + dy:ry + dy + h, rx + dx:rx + dx + w] < left)
+            bits_r.append(pr[ry + dy:ry + dy + h, rx + dx:rx + dx + w] < right)
+    bl, br = np.stack(bits_l), np.stack(bits_r)          # [offsets][H][W]
+    out = np.full((h, w, nd), 255, np.int64)
+    for d in range(min(nd, w)):
+        out[:, d:, d] = np.sum(bl[:, :, d:] != br[:, :, :w - d], axis=0)
+    return out
+
+
+@pytest.mark.parametrize("win,shape,nd,levels", [((5, 5), (17, 23), 12, 256), ((9, 7), (19, 31), 20, 256),
+                                                 ((9, 7), (21, 26), 16, 4), ((5, 5), (13, 15), 8, 3),
+                                                 ((9, 7), (5, 6), 9, 256), ((5, 5), (1, 9), 4, 2)])
+def test_cost_equals_window_comparison_count(oracle_lib, win, shape, nd, levels):
+    """The census + Hamming cost of the oracle equals the count above; few
+    grey levels put many ties (and zeros against the margin) in every window."""
+    rng = np.random.default_rng(7 + nd)
+    h, w = shape
+    left = rng.integers(0, levels, (h, w), dtype=np.uint8)
+    right = rng.integers(0, levels, (h, w), dtype=np.uint8)
+    right[:, ::3] = left[:, ::3]
+    cost = oracle_lib.cost(oracle_lib.census(left, *win), oracle_lib.census(right, *win), nd)
+    np.testing.assert_array_equal(cost.astype(np.int64), _cost_from_images(left, right, win, nd))
